@@ -1,0 +1,135 @@
+"""CPU oracle for 3D Voronoi / power cells -- TEST INFRASTRUCTURE ONLY.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
+``bench.py`` may import this package.  The product path (the HIP library and
+its Python binding) never imports it and shares no code with it.
+
+``cells()`` wraps ``liboracle.so`` (``vd_oracle.cpp``: FP64 brute-force
+clipping of the cell definition, paper Sec. 3 Eq. 1 and Sec. 4.1).
+``brute`` holds an exact-rational vertex enumeration used to pin the C++
+oracle on tiny inputs.
+
+Output layout (canonical, per requested cell, CSR over the requested cells):
+  nbr_off/nbr          neighbour site ids, ascending
+  vert_off/vert        vertex positions (FP64, global coordinates)
+  vert_code            the 3 plane codes of each vertex, ascending; a code is a
+                       site id (>= 0) or a box face -1..-6 =
+                       x_min, x_max, y_min, y_max, z_min, z_max
+                       (vertices of a cell are sorted by that triple)
+  facet_off/facet_code facets of each cell, ascending code
+  fv_off/fv            each facet's vertices (cell-local indices), CCW seen
+                       from outside, starting at the smallest index
+  vol, centroid        FP64
+  flags                1 empty, 2 degenerate (not in general position),
+                       4 coincident sites involved
+  margin               robustness margin (0 for degenerate cells, capped 1e-3)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_SRC = os.path.join(_HERE, "vd_oracle.cpp")
+
+FLAG_EMPTY = 1
+FLAG_DEGENERATE = 2
+FLAG_COINCIDENT = 4
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile liboracle.so with g++ (OpenMP)."""
+    if force or not os.path.exists(_LIB_PATH):
+        cmd = ["g++", "-O2", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o", _LIB_PATH, _SRC]
+        subprocess.run(cmd, check=True)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        lib.orc_run.restype = P
+        lib.orc_run.argtypes = [P, P, ctypes.c_int64, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int]
+        lib.orc_sizes.restype = None
+        lib.orc_sizes.argtypes = [P, P]
+        lib.orc_fetch.restype = None
+        lib.orc_fetch.argtypes = [P] * 14
+        lib.orc_free.restype = None
+        lib.orc_free.argtypes = [P]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def default_box(xyz: np.ndarray) -> np.ndarray:
+    """AABB of the sites (FP32 values widened to FP64)."""
+    x = np.asarray(xyz, dtype=np.float32)
+    return np.concatenate([x.min(axis=0), x.max(axis=0)]).astype(np.float64)
+
+
+def cells(xyz, w=None, box=None, ids=None, margin: bool = True, threads: int = 0) -> dict:
+    """Compute the cells ``ids`` (default: all) of the power diagram of
+    (xyz, w) clipped to ``box`` = [xmin, ymin, zmin, xmax, ymax, zmax]."""
+    lib = _load()
+    xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+    n = xyz.shape[0]
+    if w is not None:
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.shape == (n,)
+    box = default_box(xyz) if box is None else np.ascontiguousarray(box, dtype=np.float64)
+    if ids is not None:
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        m = ids.shape[0]
+    else:
+        m = n
+    h = lib.orc_run(_ptr(xyz), _ptr(w), n, _ptr(box), _ptr(ids), m, int(margin), int(threads))
+    if not h:
+        raise ValueError("oracle rejected its input")
+    try:
+        tot = np.zeros(4, dtype=np.int64)
+        lib.orc_sizes(h, _ptr(tot))
+        out = dict(
+            nbr_off=np.zeros(m + 1, np.int64), nbr=np.zeros(tot[0], np.int64),
+            vert_off=np.zeros(m + 1, np.int64), vert=np.zeros((tot[1], 3), np.float64),
+            vert_code=np.zeros((tot[1], 3), np.int64),
+            facet_off=np.zeros(m + 1, np.int64), facet_code=np.zeros(tot[2], np.int64),
+            fv_off=np.zeros(tot[2] + 1, np.int64), fv=np.zeros(tot[3], np.int64),
+            vol=np.zeros(m, np.float64), centroid=np.zeros((m, 3), np.float64),
+            flags=np.zeros(m, np.int32), margin=np.zeros(m, np.float64),
+        )
+        keys = ["nbr_off", "nbr", "vert_off", "vert", "vert_code", "facet_off", "facet_code",
+                "fv_off", "fv", "vol", "centroid", "flags", "margin"]
+        lib.orc_fetch(h, *[_ptr(out[k]) for k in keys])
+    finally:
+        lib.orc_free(h)
+    out["ids"] = np.arange(n, dtype=np.int64) if ids is None else ids
+    return out
+
+
+def cell_view(res: dict, t: int) -> dict:
+    """The t-th requested cell of a ``cells()`` result as plain arrays."""
+    v0, v1 = res["vert_off"][t], res["vert_off"][t + 1]
+    f0, f1 = res["facet_off"][t], res["facet_off"][t + 1]
+    facets = []
+    for f in range(f0, f1):
+        a, b = res["fv_off"][f], res["fv_off"][f + 1]
+        facets.append((int(res["facet_code"][f]), res["fv"][a:b].copy()))
+    return dict(
+        nbr=res["nbr"][res["nbr_off"][t]:res["nbr_off"][t + 1]].copy(),
+        vert=res["vert"][v0:v1].copy(), vert_code=res["vert_code"][v0:v1].copy(),
+        facets=facets, vol=float(res["vol"][t]), centroid=res["centroid"][t].copy(),
+        flags=int(res["flags"][t]), margin=float(res["margin"][t]),
+    )

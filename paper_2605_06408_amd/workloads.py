@@ -1,0 +1,147 @@
+"""Seeded synthetic site sets shaped like the paper's workloads.
+
+This module only draws random numbers; it holds none of the diagram
+arithmetic, so both the GPU path's tests and the CPU oracle may use it.
+Every generator draws in FP64 with ``numpy.random.default_rng(seed)`` (PCG64)
+and casts to FP32 at the end.  Each returns ``(xyz f32[n,3], w f32[n] or
+None, box f64[6])`` with box = [xmin, ymin, zmin, xmax, ymax, zmax].
+
+Workloads (the paper's own sets are uniform, Gaussian-cluster and
+density-gradient clouds in [-10, 10]^3 plus Radiant Foam checkpoints, none of
+which ship here; these synthetic stand-ins reproduce the distributions the
+paper stresses -- uniform, strongly clustered, surface-like and weighted):
+
+  uniform            n sites U[0,1]^3, Voronoi, box [0,1]^3
+  clustered          10% U[0,1]^3 background + 90% over 64 isotropic Gaussian
+                     clusters (centres U[0,1]^3, sigma = 10^U(-4,-1)), each
+                     point redrawn until it falls inside [0,1]^3 (truncation)
+  power_uniform      U[0,1]^3 with w = r^2, r = s exp(0.75 z), z ~ N(0,1),
+                     s = 0.5 n^(-1/3)
+  surface            95% on 250 spheres + 250 rectangles (centres U[0,1]^3,
+                     size 10^U(log10 0.01, log10 0.3), rectangle sides
+                     L x L U(0.25,1), random orientation, points in proportion
+                     to area) with N(0, 1e-3^2) normal offset, plus 5% uniform
+                     far field in [-4.5, 5.5]^3 (the 10x box); box = that box
+  power_clustered    clustered positions (same seed) with the power_uniform
+                     weight law at s = 0.005
+"""
+from __future__ import annotations
+
+import numpy as np
+
+UNIT_BOX = np.array([0.0, 0.0, 0.0, 1.0, 1.0, 1.0])
+BIG_BOX = np.array([-4.5, -4.5, -4.5, 5.5, 5.5, 5.5])
+
+
+def uniform(n: int, seed: int = 0):
+    rng = np.random.default_rng(seed)
+    xyz = rng.random((n, 3)).astype(np.float32)
+    return xyz, None, UNIT_BOX.copy()
+
+
+def _truncated_gaussian(rng, centre, sigma, count):
+    out = np.empty((count, 3))
+    filled = 0
+    while filled < count:
+        need = count - filled
+        pts = rng.normal(centre, sigma, size=(need, 3))
+        ok = np.all((pts >= 0.0) & (pts <= 1.0), axis=1)
+        pts = pts[ok]
+        out[filled:filled + len(pts)] = pts
+        filled += len(pts)
+    return out
+
+
+def clustered_positions(n: int, seed: int = 0, n_clusters: int = 64, background: float = 0.1):
+    rng = np.random.default_rng(seed)
+    n_bg = int(round(background * n))
+    n_cl = n - n_bg
+    bg = rng.random((n_bg, 3))
+    centres = rng.random((n_clusters, 3))
+    sigmas = 10.0 ** rng.uniform(-4.0, -1.0, size=n_clusters)
+    base, extra = divmod(n_cl, n_clusters)
+    parts = [bg]
+    for k in range(n_clusters):
+        cnt = base + (1 if k < extra else 0)
+        parts.append(_truncated_gaussian(rng, centres[k], sigmas[k], cnt))
+    xyz = np.concatenate(parts).astype(np.float32)
+    # FP32 rounding may land a point exactly on 1.0 but never outside [0,1]
+    return xyz
+
+
+def clustered(n: int, seed: int = 0):
+    return clustered_positions(n, seed), None, UNIT_BOX.copy()
+
+
+def _lognormal_weights(rng, n: int, s: float):
+    z = rng.normal(0.0, 1.0, size=n)
+    r = s * np.exp(0.75 * z)
+    return (r * r).astype(np.float32)
+
+
+def power_uniform(n: int, seed: int = 0):
+    rng = np.random.default_rng(seed)
+    xyz = rng.random((n, 3)).astype(np.float32)
+    s = 0.5 * n ** (-1.0 / 3.0)
+    return xyz, _lognormal_weights(rng, n, s), UNIT_BOX.copy()
+
+
+def power_clustered(n: int, seed: int = 0, s: float = 0.005):
+    xyz = clustered_positions(n, seed)
+    rng = np.random.default_rng(seed + 1_000_003)
+    return xyz, _lognormal_weights(rng, n, s), UNIT_BOX.copy()
+
+
+def _random_rotation(rng):
+    q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+    q = q * np.sign(np.diag(r))
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def surface(n: int, seed: int = 0, n_shapes: int = 500, far: float = 0.05, offset: float = 1e-3):
+    rng = np.random.default_rng(seed)
+    n_far = int(round(far * n))
+    n_surf = n - n_far
+    n_sph = n_shapes // 2
+    centres = rng.random((n_shapes, 3))
+    size = 10.0 ** rng.uniform(np.log10(0.01), np.log10(0.3), size=n_shapes)
+    aspect = rng.uniform(0.25, 1.0, size=n_shapes)
+    area = np.where(np.arange(n_shapes) < n_sph, 4.0 * np.pi * size ** 2, size * size * aspect)
+    counts = rng.multinomial(n_surf, area / area.sum())
+    parts = []
+    for k in range(n_shapes):
+        c = counts[k]
+        if c == 0:
+            continue
+        if k < n_sph:
+            d = rng.normal(size=(c, 3))
+            d /= np.linalg.norm(d, axis=1, keepdims=True)
+            pts = centres[k] + size[k] * d + rng.normal(0.0, offset, size=(c, 1)) * d
+        else:
+            rot = _random_rotation(rng)
+            u = rng.uniform(-0.5, 0.5, size=c) * size[k]
+            v = rng.uniform(-0.5, 0.5, size=c) * size[k] * aspect[k]
+            t = rng.normal(0.0, offset, size=c)
+            pts = centres[k] + u[:, None] * rot[:, 0] + v[:, None] * rot[:, 1] + t[:, None] * rot[:, 2]
+        parts.append(pts)
+    parts.append(BIG_BOX[:3] + rng.random((n_far, 3)) * (BIG_BOX[3:] - BIG_BOX[:3]))
+    xyz = np.concatenate(parts)
+    xyz = xyz[rng.permutation(len(xyz))].astype(np.float32)
+    return xyz, None, BIG_BOX.copy()
+
+
+# The five benchmark configurations at their full sizes.
+CONFIGS = {
+    "uniform_10k": (uniform, 10_000),
+    "clustered_1m": (clustered, 1_000_000),
+    "power_uniform_1m": (power_uniform, 1_000_000),
+    "surface_20m": (surface, 20_000_000),
+    "power_clustered_1m": (power_clustered, 1_000_000),
+}
+
+
+def make(name: str, seed: int = 0, n: int | None = None):
+    fn, n_full = CONFIGS[name]
+    return fn(n_full if n is None else n, seed)

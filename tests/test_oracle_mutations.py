@@ -1,0 +1,56 @@
+"""The oracle pins are sharp: plausible mistakes planted in copies of the
+oracle (on the CPU, never on the GPU) must each fail at least one pin.
+
+Every mutant is a one-line change of the kind a reader might make when
+writing the method from the paper: a weight sign in the radical plane
+(Sec. 4.2, Eq. 2), a dropped factor, a transposed operand in the vertex
+solve, a box face on the wrong side, a wrong tetrahedron centroid weight, a
+clockwise facet, a premature stop of the candidate walk, a squared radius,
+a fan without its reference point, the wrong winner among coincident sites.
+"""
+import os
+import shutil
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+MUTANTS = {
+    "weight_sign": ("h.b = 0.5 * (d2 + (site_w(in, i) - site_w(in, j)));",
+                    "h.b = 0.5 * (d2 + (site_w(in, j) - site_w(in, i)));"),
+    "drop_half": ("h.b = 0.5 * (d2 + (site_w(in, i) - site_w(in, j)));",
+                  "h.b = (d2 + (site_w(in, i) - site_w(in, j)));"),
+    "cramer_swap": ("y[k] = (A.b * bc[k] + B.b * ca[k] + C.b * ab[k]) / det;",
+                    "y[k] = (A.b * bc[k] + B.b * ab[k] + C.b * ca[k]) / det;"),
+    "box_sign": ("lo.b = p[ax] - box[ax];", "lo.b = box[ax] - p[ax];"),
+    "centroid_weight": ("mom[r] += det * (a0[r] + a1[r] + a2[r]) / 4.0;",
+                        "mom[r] += det * (a0[r] + a1[r] + a2[r]) / 3.0;"),
+    "clockwise_facets": ("std::sort(ang.begin(), ang.end());", "std::sort(ang.rbegin(), ang.rend());"),
+    "early_stop": ("if (B.cand[t].d > R) break;", "if (B.cand[t].d > 0.7 * R) break;"),
+    "coincident_tie": ("if (wt > ww || (wt == ww && ord[t] < ord[win])) win = t;",
+                       "if (wt > ww || (wt == ww && ord[t] > ord[win])) win = t;"),
+    "squared_radius": ("return std::sqrt(r2);\n}", "return r2;\n}"),
+    "fan_without_reference": ("a0[r] = f0[r] - ref[r];", "a0[r] = f0[r];"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name, tmp_path):
+    src = open(os.path.join(ROOT, "oracle", "vd_oracle.cpp")).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) == 1, "mutation site moved"
+    pkg = tmp_path / "oracle"
+    pkg.mkdir()
+    for f in ("__init__.py", "brute.py"):
+        shutil.copy(os.path.join(ROOT, "oracle", f), pkg / f)
+    (pkg / "vd_oracle.cpp").write_text(src.replace(old, new))
+    subprocess.run(["g++", "-O1", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o",
+                    str(pkg / "liboracle.so"), str(pkg / "vd_oracle.cpp")], check=True)
+    code = ("import sys; sys.path.insert(0, %r); sys.path.insert(1, %r); import pytest; "
+            "sys.exit(pytest.main(['-q', '-x', '-p', 'no:cacheprovider', %r]))"
+            % (str(tmp_path), ROOT, os.path.join(ROOT, "tests", "test_oracle_pins.py")))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=str(tmp_path),
+                       timeout=600)
+    assert r.returncode == 1, "mutant %s survived the pins:\n%s" % (name, r.stdout[-2000:])
