@@ -1,0 +1,153 @@
+/* vd.h -- C ABI of libvd: 3D Voronoi and power diagrams on one AMD MI355X.
+ *
+ * The library builds every cell of the power diagram of weighted sites
+ * independently (paper Sec. 3, Eq. 1):
+ *     C_i = B  intersected with  { x : |x-p_i|^2 - w_i <= |x-p_j|^2 - w_j  for all j != i }
+ * by clipping the box B against the bisecting (radical) planes of candidate
+ * sites (Sec. 4.1 and supplementary Sec. B).  Candidates come from a
+ * best-first walk of a bounding-volume hierarchy whose nodes also carry the
+ * largest weight below them (Sec. 4.3, Alg. 1), pruned by the directional
+ * cell bounds of Sec. 4.2.1 and the node bound of Sec. 4.2.2.  With all
+ * weights equal (or w == NULL) this is the Voronoi diagram.  Two sites are
+ * neighbours when their cells share a facet of positive area (Sec. 3).
+ *
+ * Everything is plain C: pointers, sizes and status codes.  Device pointers
+ * are HIP device memory of the context's device; `stream` is a hipStream_t
+ * passed as void* (NULL = the null stream).  All work is ordered on that
+ * stream.  No call throws; errors come back as a status, with a message from
+ * vd_last_error() (thread-local, valid until the next call on that thread).
+ *
+ * Typical use:
+ *     vd_context* ctx;  vd_create(0, &ctx);
+ *     vd_sizes sz;      vd_build(ctx, xyz, w, n, bbox, NULL, stream, &sz);
+ *     ... allocate vd_outputs arrays of the sizes in sz ...
+ *     vd_write(ctx, &out, stream);
+ *     vd_destroy(ctx);
+ */
+#ifndef VD_H
+#define VD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define VD_API __attribute__((visibility("default")))
+
+typedef enum {
+    VD_OK = 0,
+    VD_ERR_INVALID_ARG = 1,  /* bad pointer, size, option or box; non-finite input */
+    VD_ERR_HIP = 2,          /* a HIP runtime call failed */
+    VD_ERR_OOM = 3,          /* device allocation failed */
+    VD_ERR_STATE = 4,        /* vd_write without a successful vd_build */
+    VD_ERR_CAPACITY = 5      /* some cell needed more than the largest capacity */
+} vd_status;
+
+/* Per-cell flag bits (vd_outputs.flags). */
+#define VD_FLAG_EMPTY 1u      /* the cell is empty (power diagrams, coincident sites) */
+#define VD_FLAG_FP64 2u       /* some predicate of this cell was re-evaluated in FP64 */
+#define VD_FLAG_LARGE 4u      /* built by a larger-capacity pass */
+#define VD_FLAG_UNCERTAIN 8u  /* FP32 clipping met an inconsistent configuration */
+#define VD_FLAG_FAILED 16u    /* cell exceeded every capacity; outputs empty */
+
+/* Options; pass NULL for the defaults.  Zero in any field means its default. */
+typedef struct vd_options {
+    int32_t precision;  /* 1 = FP32 predicates (default), 2 = mixed FP32 / FP64 */
+    int32_t leaf_size;  /* sites per BVH leaf, 1..64 (default 16) */
+    int32_t culling;    /* 1 = directional (Sec. 4.2.1, default), 2 = isotropic radius */
+    int32_t traversal;  /* 1 = best-first (Alg. 1, default), 2 = depth-first */
+    int32_t reserved[4];
+} vd_options;
+
+/* Result sizes of the last vd_build. */
+typedef struct vd_sizes {
+    int64_t n;          /* sites */
+    int64_t n_nbr;      /* total neighbour entries */
+    int64_t n_facet;    /* total facets (site and box facets) */
+    int64_t n_vert;     /* total cell vertices (each cell lists its own) */
+    int64_t n_fv;       /* total facet-vertex entries (= 3 n_vert) */
+    int64_t n_empty;    /* empty cells */
+    int64_t n_large;    /* cells built by the larger-capacity passes */
+    int64_t n_uncertain;/* cells flagged VD_FLAG_UNCERTAIN */
+    int64_t n_failed;   /* cells flagged VD_FLAG_FAILED (status VD_ERR_CAPACITY) */
+    int64_t n_fp64;     /* cells with at least one FP64 re-evaluation */
+} vd_sizes;
+
+/* Output arrays: caller-owned device memory, sized from vd_sizes.  Rows are
+ * in the caller's original site order.  Any pointer may be NULL to skip it.
+ *   nbr_off   int64[n+1]      neighbour rows (CSR offsets)
+ *   nbr       int32[n_nbr]    neighbour site ids, ascending per row
+ *   facet_off int64[n+1]      facet rows
+ *   facet_nbr int32[n_facet]  per facet: site id (>= 0) or box face
+ *                             -1..-6 = x_min, x_max, y_min, y_max, z_min, z_max;
+ *                             ascending per row (box facets first)
+ *   fv_off    int64[n_facet+1] vertices of each facet (CSR offsets into fv)
+ *   fv        int32[n_fv]     global vertex indices (rows of `vert`),
+ *                             counter-clockwise seen from outside the cell,
+ *                             starting at the cell's lowest vertex index
+ *   vert_off  int64[n+1]      vertex rows
+ *   vert      float[n_vert*3] vertex positions
+ *   vert_planes int32[n_vert*3] the three facet codes meeting at the vertex,
+ *                             ascending (same coding as facet_nbr)
+ *   vol       float[n]        cell volume
+ *   centroid  float[n*3]      cell centroid (the site itself for empty cells)
+ *   flags     uint8[n]        VD_FLAG_* bits
+ */
+typedef struct vd_outputs {
+    int64_t* nbr_off;
+    int32_t* nbr;
+    int64_t* facet_off;
+    int32_t* facet_nbr;
+    int64_t* fv_off;
+    int32_t* fv;
+    int64_t* vert_off;
+    float* vert;
+    int32_t* vert_planes;
+    float* vol;
+    float* centroid;
+    uint8_t* flags;
+} vd_outputs;
+
+typedef struct vd_context vd_context;
+
+/* Create a context on HIP device `device`.  The context owns the device
+ * scratch reused across builds (it grows as needed and is released by
+ * vd_destroy).  A context is not thread-safe: use one per thread. */
+VD_API vd_status vd_create(int device, vd_context** ctx);
+VD_API void vd_destroy(vd_context* ctx);
+
+/* Build the diagram.
+ *   xyz   device float[n*3], row-major site positions (borrowed, read only)
+ *   w     device float[n] weights, or NULL for the Voronoi diagram
+ *   n     1 <= n <= 33554432
+ *   bbox  HOST float[6] = {xmin, ymin, zmin, xmax, ymax, zmax}, the initial
+ *         cell of every site (supplementary Sec. B starts from the sites'
+ *         bounding box); NULL = the sites' bounding box.  Sites may lie
+ *         outside it.  Each extent must be positive.
+ *   opt   NULL for defaults
+ *   sizes receives the output sizes
+ * Non-finite coordinates or weights give VD_ERR_INVALID_ARG.  Host-blocking:
+ * it synchronises `stream` to learn the output sizes.  The result stays in
+ * the context until the next vd_build. */
+VD_API vd_status vd_build(vd_context* ctx, const float* xyz, const float* w, int64_t n, const float* bbox,
+                          const vd_options* opt, void* stream, vd_sizes* sizes);
+
+/* Write the last build's diagram into caller-allocated device arrays (sizes
+ * from vd_build).  Stream-ordered, does not synchronise. */
+VD_API vd_status vd_write(vd_context* ctx, const vd_outputs* out, void* stream);
+
+/* Counters of the last build (see vd_sizes); host call, no device work. */
+VD_API vd_status vd_get_sizes(const vd_context* ctx, vd_sizes* sizes);
+
+/* Message for the last error on this thread ("" if none). */
+VD_API const char* vd_last_error(void);
+
+/* Library version string. */
+VD_API const char* vd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VD_H */

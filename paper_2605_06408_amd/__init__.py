@@ -1,1 +1,212 @@
-"""MI355X-native 3D Voronoi / power diagram construction."""
+"""MI355X-native 3D Voronoi and power diagrams (HIP, gfx950).
+
+Thin Python binding of the C ABI in ``include/vd.h`` (``libvd.so``): argument
+marshalling only.  PyTorch provides device memory and the current stream;
+every step of the construction runs in the library's HIP kernels.  If the
+library has not been built the calls raise -- there is no fallback path.
+
+    import torch, paper_2605_06408_amd as vd
+    d = vd.build(xyz_cuda_f32_nx3, w=None, bbox=[0, 0, 0, 1, 1, 1])
+    d.nbr_off, d.nbr, d.vol, d.centroid, ...
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+from collections import namedtuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvd.so")
+
+FLAG_EMPTY = 1
+FLAG_FP64 = 2
+FLAG_LARGE = 4
+FLAG_UNCERTAIN = 8
+FLAG_FAILED = 16
+
+PRECISION_FP32 = 1
+PRECISION_MIXED = 2
+CULLING_DIRECTIONAL = 1
+CULLING_ISOTROPIC = 2
+TRAVERSAL_BEST_FIRST = 1
+TRAVERSAL_DEPTH_FIRST = 2
+
+MAX_SITES = 1 << 25
+
+STATUS = {0: "VD_OK", 1: "VD_ERR_INVALID_ARG", 2: "VD_ERR_HIP", 3: "VD_ERR_OOM", 4: "VD_ERR_STATE",
+          5: "VD_ERR_CAPACITY"}
+
+
+class VDError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("culling", ctypes.c_int32),
+                ("traversal", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_int64) for k in ("n", "n_nbr", "n_facet", "n_vert", "n_fv", "n_empty", "n_large",
+                                               "n_uncertain", "n_failed", "n_fp64")]
+
+    def as_dict(self) -> dict:
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
+OUTPUT_FIELDS = ("nbr_off", "nbr", "facet_off", "facet_nbr", "fv_off", "fv", "vert_off", "vert", "vert_planes",
+                 "vol", "centroid", "flags")
+
+
+class Outputs(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_void_p) for k in OUTPUT_FIELDS]
+
+
+Diagram = namedtuple("Diagram", OUTPUT_FIELDS + ("sizes",))
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+def library_path() -> str:
+    return LIB_PATH
+
+
+def load_library():
+    """Load libvd.so; raises if it is missing (build it with ``build_library``)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError("libvd.so is not built (%s); run paper_2605_06408_amd.build_library()" % LIB_PATH)
+            lib = ctypes.CDLL(LIB_PATH)
+            P = ctypes.c_void_p
+            lib.vd_create.restype = ctypes.c_int
+            lib.vd_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+            lib.vd_destroy.restype = None
+            lib.vd_destroy.argtypes = [P]
+            lib.vd_build.restype = ctypes.c_int
+            lib.vd_build.argtypes = [P, P, P, ctypes.c_int64, P, ctypes.POINTER(Options), P, ctypes.POINTER(Sizes)]
+            lib.vd_write.restype = ctypes.c_int
+            lib.vd_write.argtypes = [P, ctypes.POINTER(Outputs), P]
+            lib.vd_get_sizes.restype = ctypes.c_int
+            lib.vd_get_sizes.argtypes = [P, ctypes.POINTER(Sizes)]
+            lib.vd_last_error.restype = ctypes.c_char_p
+            lib.vd_last_error.argtypes = []
+            lib.vd_version.restype = ctypes.c_char_p
+            lib.vd_version.argtypes = []
+            _lib = lib
+    return _lib
+
+
+def build_library(verbose: bool = False) -> str:
+    from . import buildlib
+    return buildlib.build(verbose=verbose)
+
+
+def _check(status: int, what: str):
+    if status != 0:
+        raise VDError(status, "%s: %s" % (what, load_library().vd_last_error().decode()))
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """Owns a libvd context (device scratch reused across builds)."""
+
+    def __init__(self, device=None):
+        import torch
+        self.lib = load_library()
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else torch.device(device).index or 0)
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            _check(self.lib.vd_create(self.device.index, ctypes.byref(h)), "vd_create")
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.vd_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def build_sizes(self, xyz, w=None, bbox=None, precision=PRECISION_FP32, leaf_size=0,
+                    culling=CULLING_DIRECTIONAL, traversal=TRAVERSAL_BEST_FIRST, allow_failed=False) -> Sizes:
+        """Run vd_build only (the diagram stays in the context)."""
+        import torch
+        if not (xyz.is_cuda and xyz.dtype == torch.float32 and xyz.dim() == 2 and xyz.shape[1] == 3):
+            raise ValueError("xyz must be a CUDA float32 tensor of shape [n, 3]")
+        xyz = xyz.contiguous()
+        n = xyz.shape[0]
+        if w is not None:
+            if not (w.is_cuda and w.dtype == torch.float32 and w.shape == (n,)):
+                raise ValueError("w must be a CUDA float32 tensor of shape [n]")
+            w = w.contiguous()
+        hb = None
+        if bbox is not None:
+            vals = [float(v) for v in bbox]
+            if len(vals) != 6:
+                raise ValueError("bbox must have 6 entries")
+            hb = (ctypes.c_float * 6)(*vals)
+        opt = Options(precision, leaf_size, culling, traversal)
+        sz = Sizes()
+        stream = torch.cuda.current_stream(self.device).cuda_stream
+        with torch.cuda.device(self.device):
+            st = self.lib.vd_build(self.handle, _ptr(xyz), _ptr(w), n, hb, ctypes.byref(opt),
+                                   ctypes.c_void_p(stream), ctypes.byref(sz))
+        if st == 5 and allow_failed:
+            return sz
+        _check(st, "vd_build")
+        self._keep = (xyz, w)
+        return sz
+
+    def write(self, sz: Sizes) -> Diagram:
+        """Allocate output tensors (torch caching allocator) and fill them."""
+        import torch
+        dev = self.device
+        i64, i32, f32 = torch.int64, torch.int32, torch.float32
+        n = sz.n
+        t = dict(
+            nbr_off=torch.empty(n + 1, dtype=i64, device=dev), nbr=torch.empty(sz.n_nbr, dtype=i32, device=dev),
+            facet_off=torch.empty(n + 1, dtype=i64, device=dev),
+            facet_nbr=torch.empty(sz.n_facet, dtype=i32, device=dev),
+            fv_off=torch.empty(sz.n_facet + 1, dtype=i64, device=dev), fv=torch.empty(sz.n_fv, dtype=i32, device=dev),
+            vert_off=torch.empty(n + 1, dtype=i64, device=dev), vert=torch.empty((sz.n_vert, 3), dtype=f32, device=dev),
+            vert_planes=torch.empty((sz.n_vert, 3), dtype=i32, device=dev), vol=torch.empty(n, dtype=f32, device=dev),
+            centroid=torch.empty((n, 3), dtype=f32, device=dev), flags=torch.empty(n, dtype=torch.uint8, device=dev),
+        )
+        out = Outputs(*[_ptr(t[k]) for k in OUTPUT_FIELDS])
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        with torch.cuda.device(dev):
+            _check(self.lib.vd_write(self.handle, ctypes.byref(out), ctypes.c_void_p(stream)), "vd_write")
+        return Diagram(**t, sizes=sz.as_dict())
+
+    def build(self, xyz, w=None, bbox=None, **kw) -> Diagram:
+        sz = self.build_sizes(xyz, w, bbox, **kw)
+        return self.write(sz)
+
+
+_contexts: dict = {}
+
+
+def context(device=None) -> Context:
+    import torch
+    idx = torch.cuda.current_device() if device is None else (torch.device(device).index or 0)
+    if idx not in _contexts:
+        _contexts[idx] = Context(idx)
+    return _contexts[idx]
+
+
+def build(xyz, w=None, bbox=None, **kw) -> Diagram:
+    """Power (w given) or Voronoi diagram of the sites ``xyz`` clipped to ``bbox``
+    (default: the sites' bounding box).  See ``include/vd.h`` for the layout."""
+    return context(xyz.device).build(xyz, w, bbox, **kw)

@@ -1,0 +1,379 @@
+// Host side of the C ABI declared in include/vd.h.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "vd.h"
+#include "vd_internal.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+vd_status fail(vd_status s, const std::string& msg) {
+    g_err = msg;
+    return s;
+}
+
+#define VD_HIP(x)                                                                                   \
+    do {                                                                                            \
+        hipError_t e_ = (x);                                                                        \
+        if (e_ != hipSuccess) return fail(VD_ERR_HIP, std::string(#x) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+};
+
+}  // namespace
+
+struct vd_context {
+    int device = 0;
+    int num_cu = 0;
+    // grow-only device scratch
+    DevBuf pts, spts, keys[2], vals[2], inv, mark, child, pint, pleaf, range, counters, nodes, hist, stmp, bbox,
+        bpart, misc, loc, cnt_v, cnt_f, cnt_n, vol, cen, flags, offv, offf, offn, scan_tmp, list1, list2, stats;
+    DevBuf st_vert[3], st_code[3], st_fsize[3], st_fv[3];
+    // last build
+    bool valid = false;
+    int64_t n = 0;
+    vd_sizes sizes{};
+    const uint32_t* order = nullptr;
+    int tier_slots[3] = {0, 0, 0};
+};
+
+namespace {
+
+constexpr int kTierCap[3] = {64, 256, 1024};
+
+vd_status ensure(DevBuf& b, size_t bytes) {
+    if (bytes == 0) bytes = 16;
+    if (b.cap >= bytes) return VD_OK;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        b.p = nullptr;
+        b.cap = 0;
+        if (e != hipSuccess) return fail(VD_ERR_HIP, std::string("hipFree: ") + hipGetErrorString(e));
+    }
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return fail(VD_ERR_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+    }
+    b.cap = bytes;
+    return VD_OK;
+}
+
+void release(DevBuf& b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.cap = 0;
+}
+
+template <typename T>
+T* as(DevBuf& b) {
+    return static_cast<T*>(b.p);
+}
+
+#define VD_TRY(x)                     \
+    do {                              \
+        vd_status s_ = (x);           \
+        if (s_ != VD_OK) return s_;   \
+    } while (0)
+
+vd_status ensure_stage(vd_context* c, int tier, int64_t slots) {
+    const size_t cap = (size_t)kTierCap[tier];
+    const size_t sl = (size_t)(slots > 0 ? slots : 1);
+    VD_TRY(ensure(c->st_vert[tier], sl * cap * sizeof(float4)));
+    VD_TRY(ensure(c->st_code[tier], sl * cap * sizeof(int32_t)));
+    VD_TRY(ensure(c->st_fsize[tier], sl * cap * sizeof(uint16_t)));
+    VD_TRY(ensure(c->st_fv[tier], sl * 3 * cap * sizeof(uint16_t)));
+    return VD_OK;
+}
+
+vd::Stage stage_of(vd_context* c, int tier) {
+    vd::Stage s;
+    s.cap = kTierCap[tier];
+    s.vert = as<float4>(c->st_vert[tier]);
+    s.code = as<int32_t>(c->st_code[tier]);
+    s.fsize = as<uint16_t>(c->st_fsize[tier]);
+    s.fv = as<uint16_t>(c->st_fv[tier]);
+    return s;
+}
+
+}  // namespace
+
+extern "C" {
+
+VD_API const char* vd_last_error(void) { return g_err.c_str(); }
+
+VD_API const char* vd_version(void) { return "libvd 0.1 (gfx950)"; }
+
+VD_API vd_status vd_create(int device, vd_context** out) {
+    g_err.clear();
+    if (!out) return fail(VD_ERR_INVALID_ARG, "vd_create: null output pointer");
+    *out = nullptr;
+    int count = 0;
+    VD_HIP(hipGetDeviceCount(&count));
+    if (device < 0 || device >= count) return fail(VD_ERR_INVALID_ARG, "vd_create: no such device");
+    VD_HIP(hipSetDevice(device));
+    vd_context* c = new vd_context;
+    c->device = device;
+    hipError_t e = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess || c->num_cu < 1) c->num_cu = 256;
+    *out = c;
+    return VD_OK;
+}
+
+VD_API void vd_destroy(vd_context* c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    DevBuf* all[] = {&c->pts, &c->spts, &c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->inv, &c->mark,
+                     &c->child, &c->pint, &c->pleaf, &c->range, &c->counters, &c->nodes, &c->hist, &c->stmp,
+                     &c->bbox, &c->bpart, &c->misc, &c->loc, &c->cnt_v, &c->cnt_f, &c->cnt_n, &c->vol, &c->cen,
+                     &c->flags, &c->offv, &c->offf, &c->offn, &c->scan_tmp, &c->list1, &c->list2, &c->stats};
+    for (DevBuf* b : all) release(*b);
+    for (int t = 0; t < 3; ++t) {
+        release(c->st_vert[t]);
+        release(c->st_code[t]);
+        release(c->st_fsize[t]);
+        release(c->st_fv[t]);
+    }
+    delete c;
+}
+
+VD_API vd_status vd_get_sizes(const vd_context* c, vd_sizes* sizes) {
+    if (!c || !sizes) return fail(VD_ERR_INVALID_ARG, "vd_get_sizes: null argument");
+    if (!c->valid) return fail(VD_ERR_STATE, "vd_get_sizes: no successful build");
+    *sizes = c->sizes;
+    return VD_OK;
+}
+
+VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64_t n, const float* bbox,
+                          const vd_options* opt, void* stream, vd_sizes* sizes) {
+    g_err.clear();
+    if (!c || !xyz || !sizes) return fail(VD_ERR_INVALID_ARG, "vd_build: null argument");
+    c->valid = false;
+    if (n < 1 || n > vd::kMaxSites)
+        return fail(VD_ERR_INVALID_ARG, "vd_build: n must be in [1, " + std::to_string(vd::kMaxSites) + "]");
+    vd_options o{};
+    if (opt) o = *opt;
+    if (o.precision == 0) o.precision = 1;
+    if (o.leaf_size == 0) o.leaf_size = vd::kDefaultLeaf;
+    if (o.culling == 0) o.culling = 1;
+    if (o.traversal == 0) o.traversal = 1;
+    if (o.precision < 1 || o.precision > 2) return fail(VD_ERR_INVALID_ARG, "vd_build: precision must be 1 or 2");
+    if (o.leaf_size < 1 || o.leaf_size > vd::kMaxLeaf)
+        return fail(VD_ERR_INVALID_ARG, "vd_build: leaf_size must be in [1, 64]");
+    if (o.culling < 1 || o.culling > 2) return fail(VD_ERR_INVALID_ARG, "vd_build: culling must be 1 or 2");
+    if (o.traversal < 1 || o.traversal > 2) return fail(VD_ERR_INVALID_ARG, "vd_build: traversal must be 1 or 2");
+    if (bbox) {
+        for (int k = 0; k < 6; ++k)
+            if (!std::isfinite(bbox[k])) return fail(VD_ERR_INVALID_ARG, "vd_build: non-finite bbox");
+        for (int k = 0; k < 3; ++k)
+            if (!(bbox[3 + k] > bbox[k])) return fail(VD_ERR_INVALID_ARG, "vd_build: bbox extent must be positive");
+    }
+    VD_HIP(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t N = (size_t)n;
+
+    VD_TRY(ensure(c->pts, N * sizeof(float4)));
+    VD_TRY(ensure(c->spts, N * sizeof(float4)));
+    for (int k = 0; k < 2; ++k) {
+        VD_TRY(ensure(c->keys[k], N * sizeof(uint64_t)));
+        VD_TRY(ensure(c->vals[k], N * sizeof(uint32_t)));
+    }
+    VD_TRY(ensure(c->inv, N * sizeof(uint32_t)));
+    VD_TRY(ensure(c->mark, N));
+    VD_TRY(ensure(c->child, N * sizeof(int2)));
+    VD_TRY(ensure(c->pint, N * sizeof(int)));
+    VD_TRY(ensure(c->pleaf, N * sizeof(int)));
+    VD_TRY(ensure(c->range, N * sizeof(int2)));
+    VD_TRY(ensure(c->counters, N * sizeof(uint32_t)));
+    VD_TRY(ensure(c->nodes, N * sizeof(vd::Node)));
+    VD_TRY(ensure(c->hist, vd::radix_hist_size(n) * sizeof(uint32_t)));
+    VD_TRY(ensure(c->stmp, vd::scan_tmp_size((int64_t)vd::radix_hist_size(n)) * sizeof(uint64_t)));
+    VD_TRY(ensure(c->bbox, 8 * sizeof(float)));
+    VD_TRY(ensure(c->bpart, 1024 * 6 * sizeof(float)));
+    VD_TRY(ensure(c->misc, 16 * sizeof(uint32_t)));
+    VD_TRY(ensure(c->loc, N * sizeof(uint32_t)));
+    VD_TRY(ensure(c->cnt_v, N * sizeof(uint32_t)));
+    VD_TRY(ensure(c->cnt_f, N * sizeof(uint32_t)));
+    VD_TRY(ensure(c->cnt_n, N * sizeof(uint32_t)));
+    VD_TRY(ensure(c->vol, N * sizeof(float)));
+    VD_TRY(ensure(c->cen, 3 * N * sizeof(float)));
+    VD_TRY(ensure(c->flags, N));
+    VD_TRY(ensure(c->offv, (N + 1) * sizeof(int64_t)));
+    VD_TRY(ensure(c->offf, (N + 1) * sizeof(int64_t)));
+    VD_TRY(ensure(c->offn, (N + 1) * sizeof(int64_t)));
+    VD_TRY(ensure(c->scan_tmp, vd::scan_tmp_size(n) * sizeof(int64_t)));
+    VD_TRY(ensure(c->list1, N * sizeof(uint32_t)));
+    VD_TRY(ensure(c->list2, N * sizeof(uint32_t)));
+    VD_TRY(ensure(c->stats, vd::kStatCount * sizeof(unsigned long long)));
+    VD_TRY(ensure_stage(c, 0, n));
+
+    // misc: [0] error bits, [1..3] work counters, [4] tier-1 list count, [5] tier-2 list count
+    uint32_t* misc = as<uint32_t>(c->misc);
+    VD_HIP(hipMemsetAsync(misc, 0, 16 * sizeof(uint32_t), s));
+    VD_HIP(hipMemsetAsync(c->stats.p, 0, vd::kStatCount * sizeof(unsigned long long), s));
+    float4* pts = as<float4>(c->pts);
+    float* dbbox = as<float>(c->bbox);
+    VD_HIP(vd::launch_pack(xyz, w, n, pts, misc, s));
+    if (bbox) {
+        VD_HIP(hipMemcpyAsync(dbbox, bbox, 6 * sizeof(float), hipMemcpyHostToDevice, s));
+        VD_HIP(vd::launch_check_bbox(dbbox, misc, s));
+    } else {
+        VD_HIP(vd::launch_bbox(pts, n, as<float>(c->bpart), 1024, dbbox, misc, s));
+    }
+    VD_HIP(vd::launch_morton(pts, n, dbbox, as<uint64_t>(c->keys[0]), as<uint32_t>(c->vals[0]), s));
+    bool in_tmp = false;
+    VD_HIP(vd::radix_sort(as<uint64_t>(c->keys[0]), as<uint32_t>(c->vals[0]), as<uint64_t>(c->keys[1]),
+                          as<uint32_t>(c->vals[1]), n, 63, as<uint32_t>(c->hist), as<uint32_t>(c->stmp), s,
+                          &in_tmp));
+    const uint64_t* skeys = as<uint64_t>(c->keys[in_tmp ? 1 : 0]);
+    const uint32_t* order = as<uint32_t>(c->vals[in_tmp ? 1 : 0]);
+    float4* spts = as<float4>(c->spts);
+    VD_HIP(vd::launch_gather(pts, order, n, spts, as<uint32_t>(c->inv), s));
+    VD_HIP(vd::launch_losers(spts, skeys, order, n, as<uint8_t>(c->mark), s));
+    uint32_t root;
+    if (n > o.leaf_size) {
+        VD_HIP(hipMemsetAsync(c->counters.p, 0, N * sizeof(uint32_t), s));
+        VD_HIP(vd::launch_karras(skeys, n, as<int2>(c->child), as<int>(c->pint), as<int>(c->pleaf),
+                                 as<int2>(c->range), s));
+        VD_HIP(vd::launch_bounds(spts, n, as<int2>(c->child), as<int>(c->pint), as<int>(c->pleaf),
+                                 as<int2>(c->range), as<uint32_t>(c->counters), as<vd::Node>(c->nodes), o.leaf_size,
+                                 s));
+        root = 0;
+    } else {
+        root = vd::leaf_ref(0u, (uint32_t)n);
+    }
+
+    vd::ClipArgs a{};
+    a.pts = spts;
+    a.order = order;
+    a.nodes = as<vd::Node>(c->nodes);
+    a.root = root;
+    a.bbox = dbbox;
+    a.n = n;
+    a.leaf_size = o.leaf_size;
+    a.culling = o.culling;
+    a.traversal = o.traversal;
+    a.precision = o.precision;
+    a.loc = as<uint32_t>(c->loc);
+    a.cnt_v = as<uint32_t>(c->cnt_v);
+    a.cnt_f = as<uint32_t>(c->cnt_f);
+    a.cnt_n = as<uint32_t>(c->cnt_n);
+    a.vol = as<float>(c->vol);
+    a.cen = as<float>(c->cen);
+    a.flags = as<uint8_t>(c->flags);
+    a.stats = as<unsigned long long>(c->stats);
+
+    // tier 0: every cell
+    a.tier = 0;
+    a.work_counter = misc + 1;
+    a.list = nullptr;
+    a.list_count = nullptr;
+    a.next_list = as<uint32_t>(c->list1);
+    a.next_count = misc + 4;
+    a.stage = stage_of(c, 0);
+    c->tier_slots[0] = (int)n;
+    VD_HIP(vd::launch_clip(a, vd::clip_grid_waves(0, c->num_cu), s));
+    uint32_t hmisc[16];
+    VD_HIP(hipMemcpyAsync(hmisc, misc, sizeof(hmisc), hipMemcpyDeviceToHost, s));
+    VD_HIP(hipStreamSynchronize(s));
+    if (hmisc[0] & 1u) return fail(VD_ERR_INVALID_ARG, "vd_build: non-finite site coordinate or weight");
+    if (hmisc[0] & 2u) return fail(VD_ERR_INVALID_ARG, "vd_build: degenerate bounding box");
+    // larger tiers for the cells that outgrew the previous one
+    for (int tier = 1; tier < 3; ++tier) {
+        const uint32_t cnt = hmisc[3 + tier];
+        c->tier_slots[tier] = (int)cnt;
+        if (cnt == 0) break;
+        VD_TRY(ensure_stage(c, tier, cnt));
+        a.tier = tier;
+        a.work_counter = misc + 1 + tier;
+        a.list = as<uint32_t>(tier == 1 ? c->list1 : c->list2);
+        a.list_count = misc + 3 + tier;
+        a.next_list = tier == 1 ? as<uint32_t>(c->list2) : nullptr;
+        a.next_count = tier == 1 ? misc + 5 : nullptr;
+        a.stage = stage_of(c, tier);
+        int waves = vd::clip_grid_waves(tier, c->num_cu);
+        if ((int64_t)waves > (int64_t)cnt) waves = (int)cnt;
+        VD_HIP(vd::launch_clip(a, waves, s));
+        VD_HIP(hipMemcpyAsync(hmisc, misc, sizeof(hmisc), hipMemcpyDeviceToHost, s));
+        VD_HIP(hipStreamSynchronize(s));
+    }
+    VD_HIP(vd::scan_counts(as<uint32_t>(c->cnt_v), n, as<int64_t>(c->offv), as<int64_t>(c->scan_tmp), s));
+    VD_HIP(vd::scan_counts(as<uint32_t>(c->cnt_f), n, as<int64_t>(c->offf), as<int64_t>(c->scan_tmp), s));
+    VD_HIP(vd::scan_counts(as<uint32_t>(c->cnt_n), n, as<int64_t>(c->offn), as<int64_t>(c->scan_tmp), s));
+    int64_t tot[3];
+    unsigned long long st[vd::kStatCount];
+    VD_HIP(hipMemcpyAsync(&tot[0], as<int64_t>(c->offv) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    VD_HIP(hipMemcpyAsync(&tot[1], as<int64_t>(c->offf) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    VD_HIP(hipMemcpyAsync(&tot[2], as<int64_t>(c->offn) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    VD_HIP(hipMemcpyAsync(st, c->stats.p, sizeof(st), hipMemcpyDeviceToHost, s));
+    VD_HIP(hipStreamSynchronize(s));
+
+    vd_sizes z{};
+    z.n = n;
+    z.n_vert = tot[0];
+    z.n_facet = tot[1];
+    z.n_nbr = tot[2];
+    z.n_fv = 3 * tot[0];
+    z.n_empty = (int64_t)st[vd::kStatEmpty];
+    z.n_large = (int64_t)st[vd::kStatLarge];
+    z.n_uncertain = (int64_t)st[vd::kStatUncertain];
+    z.n_failed = (int64_t)st[vd::kStatFailed];
+    z.n_fp64 = (int64_t)st[vd::kStatFP64];
+    c->sizes = z;
+    c->n = n;
+    c->order = order;
+    c->valid = true;
+    *sizes = z;
+    if (z.n_failed > 0)
+        return fail(VD_ERR_CAPACITY, "vd_build: " + std::to_string(z.n_failed) +
+                                         " cells exceeded the largest capacity (1024 vertices); they are flagged");
+    return VD_OK;
+}
+
+VD_API vd_status vd_write(vd_context* c, const vd_outputs* out, void* stream) {
+    g_err.clear();
+    if (!c || !out) return fail(VD_ERR_INVALID_ARG, "vd_write: null argument");
+    if (!c->valid) return fail(VD_ERR_STATE, "vd_write: no successful build");
+    VD_HIP(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = c->n;
+    vd::WriteArgs a{};
+    a.n = n;
+    a.inv = as<uint32_t>(c->inv);
+    a.loc = as<uint32_t>(c->loc);
+    for (int t = 0; t < 3; ++t) a.stage[t] = stage_of(c, t);
+    a.cnt_v = as<uint32_t>(c->cnt_v);
+    a.cnt_f = as<uint32_t>(c->cnt_f);
+    a.cnt_n = as<uint32_t>(c->cnt_n);
+    a.off_v = as<int64_t>(c->offv);
+    a.off_f = as<int64_t>(c->offf);
+    a.off_n = as<int64_t>(c->offn);
+    a.nbr = out->nbr;
+    a.facet_nbr = out->facet_nbr;
+    a.fv_off = out->fv_off;
+    a.fv = out->fv;
+    a.vert = out->vert;
+    a.vert_planes = out->vert_planes;
+    if (a.nbr || a.facet_nbr || a.fv_off || a.fv || a.vert || a.vert_planes) VD_HIP(vd::launch_write(a, s));
+    const size_t off_bytes = (size_t)(n + 1) * sizeof(int64_t);
+    if (out->nbr_off) VD_HIP(hipMemcpyAsync(out->nbr_off, c->offn.p, off_bytes, hipMemcpyDeviceToDevice, s));
+    if (out->facet_off) VD_HIP(hipMemcpyAsync(out->facet_off, c->offf.p, off_bytes, hipMemcpyDeviceToDevice, s));
+    if (out->vert_off) VD_HIP(hipMemcpyAsync(out->vert_off, c->offv.p, off_bytes, hipMemcpyDeviceToDevice, s));
+    if (out->fv_off) VD_HIP(vd::launch_set_i64(out->fv_off + c->sizes.n_facet, c->sizes.n_fv, s));
+    if (out->vol) VD_HIP(hipMemcpyAsync(out->vol, c->vol.p, (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (out->centroid)
+        VD_HIP(hipMemcpyAsync(out->centroid, c->cen.p, 3 * (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, s));
+    if (out->flags) VD_HIP(hipMemcpyAsync(out->flags, c->flags.p, (size_t)n, hipMemcpyDeviceToDevice, s));
+    return VD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,959 @@
+// Per-site traversal and clipping: the hot loop of the method.
+//
+// What is computed (paper Sec. 4, Alg. 1, supplementary Sec. B): for every
+// site p_i the cell starts as the clip box and is cut by the half-spaces
+// a.y <= b (frame centred on p_i, a = p_j - p_i, b = (|a|^2 + w_i - w_j)/2)
+// of candidate sites.  Candidates come from a best-first walk of the BVH:
+// a node is skipped when the lower bound on the plane distance of any site
+// in it (Sec. 4.2.2: d/2 + min(0, w_i - w_max)/(2d), d = distance from p_i
+// to the node box) exceeds the directional radius of the cell toward the
+// node (Sec. 4.2.1: distance from p_i to the far corner of the cell's AABB
+// in each octant the node occupies); a site in a leaf is skipped when its
+// plane distance b/|a| exceeds the directional radius of its own octant.
+// Far children are queued with their bound as key, the minimum is popped and
+// re-tested against the shrunken cell (Alg. 1).
+//
+// How it maps to CDNA4: one 64-wide wavefront owns one cell.  Vertex v lives
+// in lane v % 64 (VPL vertices per lane), in registers: its position, the
+// three planes meeting there, ordered so that their outward normals have a
+// positive determinant, and the three vertices across its edges (edge k is
+// the one that leaves plane k).  Planes live in LDS.  Classifying all
+// vertices against a plane is one ballot; the hole left by removed vertices
+// is closed by one new vertex per crossing edge (supplementary Sec. B): a
+// kept vertex with a removed neighbour across edge k = (planes p_k+1, p_k+2)
+// spawns the vertex (h, p_k+2, p_k+1), and new vertices find each other
+// through two LDS tables keyed by their old planes.  The node queue is spread
+// one entry per lane (min-pop is a wave reduction), node children are tested
+// by two lanes at once, and a leaf's sites are tested by one lane each.
+// Cells that outgrow a tier's capacity are handed to the next tier (256 and
+// 1024 vertices).  The paper's own kernel keeps one cell per thread in
+// global memory; that layout was made for its GPUs and is not used here.
+#include "vd_internal.h"
+
+namespace vd {
+namespace {
+
+constexpr float kU = 5.9604645e-08f;  // FP32 unit roundoff 2^-24
+constexpr double kU64 = 1.1102230246251565e-16;
+
+enum ClipResult { kNone = 0, kChanged = 1, kEmptied = 2, kOverflow = 3 };
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint32_t mbcnt(uint64_t m) {
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+__device__ __forceinline__ int popc(uint64_t m) { return __popcll(m); }
+__device__ __forceinline__ int lowest(uint64_t m) { return __builtin_ctzll(m); }
+__device__ __forceinline__ float rdl(float v, int l) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), l));
+}
+__device__ __forceinline__ uint32_t rdl(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
+__device__ __forceinline__ int rdl(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
+__device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ float wmin(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return uni(v);
+}
+__device__ __forceinline__ float wmax(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return uni(v);
+}
+__device__ __forceinline__ float wsum(float v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return uni(v);
+}
+__device__ __forceinline__ uint32_t wsum_u(uint32_t v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+// Orders this wave's LDS accesses: all writes before the fence are visible to
+// all lanes' reads after it (one wave, so no workgroup barrier is needed).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__device__ __forceinline__ uint32_t f10(uint32_t w, int k) { return (w >> (10 * k)) & 1023u; }
+__device__ __forceinline__ uint32_t set10(uint32_t w, int k, uint32_t v) {
+    return (w & ~(1023u << (10 * k))) | (v << (10 * k));
+}
+
+template <int VPL>
+struct WaveMem {
+    static constexpr int CAP = 64 * VPL;
+    float4 pl[CAP];        // planes: a.xyz, b (frame of the site)
+    float psb[CAP];        // size of the terms b is formed from (error scale)
+    int32_t pcode[CAP];    // Morton index of the plane's site, or box code -1..-6
+    uint32_t ta[CAP];      // clip: new vertex by first old plane | finalize: plane rank
+    uint32_t tb[CAP];      // clip: new vertex by second old plane | finalize: facet size
+    uint32_t edge[CAP];    // clip: crossing edges by rank | finalize: facet anchor
+    uint32_t sor[CAP];     // clip: free slot of rank | finalize: vertex renumbering
+    uint32_t vtri[CAP];    // finalize: planes of each vertex
+    uint32_t vadj[CAP];    // finalize: neighbours of each vertex
+    float4 vpos[CAP];      // finalize: positions
+    int32_t key[CAP];      // finalize and gc: output codes, used flags
+    uint8_t outf[CAP];     // outside flags by vertex index (VPL > 1)
+};
+
+// Error-free-ish helpers for the FP64 re-evaluation of a doubtful side test.
+struct P64 {
+    double a0, a1, a2, b;
+};
+
+template <int VPL>
+struct Cell {
+    static constexpr int CAP = 64 * VPL;
+    WaveMem<VPL>& M;
+    const ClipArgs& A;
+    const uint32_t ln;
+    uint32_t serial;
+    // site
+    float px, py, pz, pw;
+    uint32_t self;
+    uint32_t flags;
+    // vertices: slot s of this lane is vertex s*64 + lane
+    float y0[VPL], y1[VPL], y2[VPL], ev[VPL];
+    uint32_t vt[VPL], va[VPL];
+    uint64_t alive[VPL];
+    int np;
+    // bounds of the current cell (uniform)
+    float hx2, hy2, hz2, lx2, ly2, lz2, rmax2, riso2;
+    // queue (one entry per lane and slot)
+    uint32_t qe[VPL];
+    float qk[VPL];
+    int qn;
+
+    __device__ Cell(WaveMem<VPL>& m, const ClipArgs& a) : M(m), A(a), ln(lane_id()), serial(1) {}
+
+    // ------------------------------------------------------------ setup
+    __device__ bool init(uint32_t k) {
+        self = k;
+        float4 s = A.pts[k];
+        px = s.x; py = s.y; pz = s.z; pw = s.w;
+        flags = 0;
+        qn = 0;
+        if (pw == -INFINITY) return false;  // coincident with a heavier site
+        const float lo[3] = {A.bbox[0] - px, A.bbox[1] - py, A.bbox[2] - pz};
+        const float hi[3] = {A.bbox[3] - px, A.bbox[4] - py, A.bbox[5] - pz};
+        if (ln < 6) {
+            int ax = ln >> 1, side = ln & 1;
+            float a[3] = {0.f, 0.f, 0.f};
+            a[ax] = side ? 1.f : -1.f;
+            float b = side ? hi[ax] : -lo[ax];
+            M.pl[ln] = make_float4(a[0], a[1], a[2], b);
+            M.psb[ln] = fabsf(b);
+            M.pcode[ln] = -(int)(ln + 1);
+        }
+#pragma unroll
+        for (int s2 = 0; s2 < VPL; ++s2) alive[s2] = 0;
+        alive[0] = 0xFFull;
+        {
+            uint32_t c = ln & 7;
+            uint32_t sx = c & 1, sy = (c >> 1) & 1, sz = (c >> 2) & 1;
+            uint32_t X = sx, Y = 2 + sy, Z = 4 + sz;
+            bool pos = ((sx ^ sy ^ sz) & 1) == 1;  // product of the three normal signs > 0
+            uint32_t p1 = pos ? Y : Z, p2 = pos ? Z : Y;
+            uint32_t ax1 = p1 >> 1, ax2 = p2 >> 1;
+            vt[0] = X | (p1 << 10) | (p2 << 20);
+            va[0] = (c ^ 1u) | ((c ^ (1u << ax1)) << 10) | ((c ^ (1u << ax2)) << 20);
+            y0[0] = sx ? hi[0] : lo[0];
+            y1[0] = sy ? hi[1] : lo[1];
+            y2[0] = sz ? hi[2] : lo[2];
+            ev[0] = fabsf(y0[0]) + fabsf(y1[0]) + fabsf(y2[0]);
+        }
+        np = 6;
+        wave_sync();
+        update_bounds();
+        return true;
+    }
+
+    __device__ void update_bounds() {
+        float mn0 = INFINITY, mn1 = INFINITY, mn2 = INFINITY, mx0 = -INFINITY, mx1 = -INFINITY, mx2 = -INFINITY,
+              r2 = 0.f;
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) {
+            if ((alive[s] >> ln) & 1) {
+                mn0 = fminf(mn0, y0[s]); mn1 = fminf(mn1, y1[s]); mn2 = fminf(mn2, y2[s]);
+                mx0 = fmaxf(mx0, y0[s]); mx1 = fmaxf(mx1, y1[s]); mx2 = fmaxf(mx2, y2[s]);
+                r2 = fmaxf(r2, fmaf(y0[s], y0[s], fmaf(y1[s], y1[s], y2[s] * y2[s])));
+            }
+        }
+        float l0 = wmin(mn0), l1 = wmin(mn1), l2 = wmin(mn2);
+        float h0 = wmax(mx0), h1 = wmax(mx1), h2 = wmax(mx2);
+        riso2 = wmax(r2);
+        hx2 = h0 * h0; hy2 = h1 * h1; hz2 = h2 * h2;
+        lx2 = l0 * l0; ly2 = l1 * l1; lz2 = l2 * l2;
+        rmax2 = fmaxf(hx2, lx2) + fmaxf(hy2, ly2) + fmaxf(hz2, lz2);
+    }
+
+    // Squared radius of the cell toward direction a (far AABB corner of the
+    // octant of a; zero components count as positive).
+    __device__ __forceinline__ float radius2_toward(float ax, float ay, float az) const {
+        if (A.culling == 2) return riso2;
+        return (ax >= 0.f ? hx2 : lx2) + (ay >= 0.f ? hy2 : ly2) + (az >= 0.f ? hz2 : lz2);
+    }
+
+    // ------------------------------------------------------------ FP64 side test
+    __device__ P64 plane64(int32_t code, double qx, double qy, double qz, double qw) const {
+        P64 r;
+        if (code < 0) {
+            int c = -code - 1, ax = c >> 1, side = c & 1;
+            double p[3] = {qx, qy, qz};
+            r.a0 = r.a1 = r.a2 = 0.0;
+            double sgn = side ? 1.0 : -1.0;
+            if (ax == 0) r.a0 = sgn; else if (ax == 1) r.a1 = sgn; else r.a2 = sgn;
+            r.b = side ? ((double)A.bbox[3 + ax] - p[ax]) : (p[ax] - (double)A.bbox[ax]);
+        } else {
+            float4 q = A.pts[code];
+            r.a0 = (double)q.x - qx; r.a1 = (double)q.y - qy; r.a2 = (double)q.z - qz;
+            r.b = 0.5 * (r.a0 * r.a0 + r.a1 * r.a1 + r.a2 * r.a2 + (qw - (double)q.w));
+        }
+        return r;
+    }
+
+    // Side of vertex (planes t) w.r.t. plane h, recomputed in FP64 from the
+    // input coordinates.  Returns +1 outside, -1 inside, 0 undecided.
+    __device__ int side64(uint32_t t, const P64& h) const {
+        double qx = px, qy = py, qz = pz, qw = pw;
+        P64 A0 = plane64(M.pcode[f10(t, 0)], qx, qy, qz, qw);
+        P64 B0 = plane64(M.pcode[f10(t, 1)], qx, qy, qz, qw);
+        P64 C0 = plane64(M.pcode[f10(t, 2)], qx, qy, qz, qw);
+        double bc0 = B0.a1 * C0.a2 - B0.a2 * C0.a1, bc1 = B0.a2 * C0.a0 - B0.a0 * C0.a2,
+               bc2 = B0.a0 * C0.a1 - B0.a1 * C0.a0;
+        double ca0 = C0.a1 * A0.a2 - C0.a2 * A0.a1, ca1 = C0.a2 * A0.a0 - C0.a0 * A0.a2,
+               ca2 = C0.a0 * A0.a1 - C0.a1 * A0.a0;
+        double ab0 = A0.a1 * B0.a2 - A0.a2 * B0.a1, ab1 = A0.a2 * B0.a0 - A0.a0 * B0.a2,
+               ab2 = A0.a0 * B0.a1 - A0.a1 * B0.a0;
+        double det = A0.a0 * bc0 + A0.a1 * bc1 + A0.a2 * bc2;
+        double n0 = A0.b * bc0 + B0.b * ca0 + C0.b * ab0;
+        double n1 = A0.b * bc1 + B0.b * ca1 + C0.b * ab1;
+        double n2 = A0.b * bc2 + B0.b * ca2 + C0.b * ab2;
+        // s * det = a_h . n - b_h det, evaluated without dividing
+        double s = h.a0 * n0 + h.a1 * n1 + h.a2 * n2 - h.b * det;
+        if (det < 0) s = -s;
+        double scale = (fabs(h.a0) + fabs(h.a1) + fabs(h.a2)) * (fabs(n0) + fabs(n1) + fabs(n2)) + fabs(h.b * det);
+        if (fabs(s) <= 64.0 * kU64 * scale) return 0;
+        return s > 0 ? 1 : -1;
+    }
+
+    // ------------------------------------------------------------ clip
+    // mode 0: plain FP32 signs; 1: doubtful signs re-evaluated in FP64;
+    // 2: doubtful signs taken as inside (fallback after an inconsistency).
+    __device__ void classify(float ax, float ay, float az, float b, float sbh, int32_t hcode, int mode,
+                             uint64_t* R) {
+        const float an1 = fabsf(ax) + fabsf(ay) + fabsf(az);
+        uint64_t amb_any = 0;
+        bool amb[VPL];
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) {
+            float sv = fmaf(ax, y0[s], fmaf(ay, y1[s], fmaf(az, y2[s], -b)));
+            bool al = (alive[s] >> ln) & 1;
+            bool o = al && sv > 0.f;
+            amb[s] = false;
+            if (mode != 0) {
+                float beta = 32.f * kU * (an1 * ev[s] + sbh);
+                amb[s] = al && fabsf(sv) <= beta;
+                if (amb[s] && mode == 2) o = false;
+            }
+            R[s] = ballot(o);
+            amb_any |= ballot(amb[s]);
+        }
+        if (mode == 1 && amb_any) {
+            flags |= kFlagFP64;
+            P64 h = plane64(hcode, (double)px, (double)py, (double)pz, (double)pw);
+#pragma unroll
+            for (int s = 0; s < VPL; ++s) {
+                bool o = (R[s] >> ln) & 1;
+                bool unsure = false;
+                if (amb[s]) {
+                    int sg = side64(vt[s], h);
+                    o = sg > 0;
+                    unsure = sg == 0;
+                }
+                R[s] = ballot(o);
+                if (ballot(unsure)) flags |= kFlagUncertain;
+            }
+        }
+    }
+
+    // Tries the clip with the given outside masks; on an inconsistent
+    // boundary returns false and leaves the cell untouched.
+    __device__ int apply(const uint64_t* R, float ax, float ay, float az, float b, float sbh, int32_t hcode,
+                         bool* consistent) {
+        *consistent = true;
+        bool any = false, all = true;
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) {
+            any |= R[s] != 0;
+            all &= R[s] == alive[s];
+        }
+        if (!any) return kNone;
+        if (all) return kEmptied;
+        if (np >= CAP) {
+            gc();
+            if (np >= CAP) return kOverflow;
+        }
+        if constexpr (VPL > 1) {
+#pragma unroll
+            for (int s = 0; s < VPL; ++s) M.outf[s * 64 + ln] = (uint8_t)((R[s] >> ln) & 1);
+            wave_sync();
+        }
+        auto is_out = [&](uint32_t v) -> bool {
+            if constexpr (VPL == 1) return (R[0] >> v) & 1;
+            else return M.outf[v] != 0;
+        };
+        // crossing edges of kept vertices, ranked over the wave
+        uint32_t cross[VPL], pre[VPL];
+        uint32_t m = 0;
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) {
+            bool kept = ((alive[s] & ~R[s]) >> ln) & 1;
+            uint32_t c = 0, cnt = 0;
+            if (kept) {
+#pragma unroll
+                for (int e = 0; e < 3; ++e)
+                    if (is_out(f10(va[s], e))) {
+                        c |= 1u << e;
+                        ++cnt;
+                    }
+            }
+            cross[s] = c;
+            uint64_t b0 = ballot(cnt & 1), b1 = ballot(cnt & 2);
+            pre[s] = m + mbcnt(b0) + 2 * mbcnt(b1);
+            m += popc(b0) + 2 * popc(b1);
+        }
+        // free slots (dead or removed), ranked
+        uint32_t nfree = 0, frank[VPL];
+        uint64_t fr[VPL];
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) {
+            fr[s] = ~alive[s] | R[s];
+            frank[s] = nfree + mbcnt(fr[s]);
+            nfree += popc(fr[s]);
+        }
+        if (m > nfree) return kOverflow;
+        const uint32_t h = (uint32_t)np;
+        ++serial;
+        if (serial >= 0xFFFFEu) {  // tag space exhausted: clear the tables
+            for (int q = ln; q < CAP; q += 64) { M.ta[q] = 0; M.tb[q] = 0; }
+            serial = 1;
+        }
+        const uint32_t tag = serial << 12;
+#pragma unroll
+        for (int s = 0; s < VPL; ++s)
+            if (((fr[s] >> ln) & 1) && frank[s] < m) M.sor[frank[s]] = s * 64 + ln;
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) {
+            if (cross[s]) {
+                uint32_t j = pre[s];
+#pragma unroll
+                for (int e = 0; e < 3; ++e)
+                    if ((cross[s] >> e) & 1) {
+                        uint32_t x = f10(vt[s], (e + 2) % 3), y = f10(vt[s], (e + 1) % 3);
+                        M.edge[j++] = (uint32_t)(s * 64 + ln) | (x << 10) | (y << 20);
+                    }
+            }
+        }
+        wave_sync();
+        bool isnew[VPL];
+        uint32_t rec[VPL];
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) {
+            isnew[s] = ((fr[s] >> ln) & 1) && frank[s] < m;
+            rec[s] = 0;
+            if (isnew[s]) {
+                rec[s] = M.edge[frank[s]];
+                uint32_t me = tag | (uint32_t)(s * 64 + ln);
+                M.ta[f10(rec[s], 1)] = me;
+                M.tb[f10(rec[s], 2)] = me;
+            }
+        }
+        wave_sync();
+        bool bad = false;
+        uint32_t nb1[VPL], nb2[VPL];
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) {
+            nb1[s] = nb2[s] = 0;
+            if (isnew[s]) {
+                uint32_t me = tag | (uint32_t)(s * 64 + ln);
+                uint32_t x = f10(rec[s], 1), y = f10(rec[s], 2);
+                uint32_t a1 = M.ta[y], a2 = M.tb[x];
+                bad |= M.ta[x] != me || M.tb[y] != me;
+                bad |= (a1 & ~4095u) != tag || (a2 & ~4095u) != tag;
+                nb1[s] = a1 & 4095u;
+                nb2[s] = a2 & 4095u;
+            }
+        }
+        if (ballot(bad)) {
+            *consistent = false;
+            return kNone;
+        }
+        // commit: kept vertices point at their new neighbours
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) {
+            if (cross[s]) {
+                uint32_t j = pre[s];
+#pragma unroll
+                for (int e = 0; e < 3; ++e)
+                    if ((cross[s] >> e) & 1) va[s] = set10(va[s], e, M.sor[j++]);
+            }
+        }
+        // new vertices: planes (h, x, y), position by Cramer's rule
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) {
+            if (isnew[s]) {
+                uint32_t x = f10(rec[s], 1), y = f10(rec[s], 2);
+                vt[s] = h | (x << 10) | (y << 20);
+                va[s] = f10(rec[s], 0) | (nb1[s] << 10) | (nb2[s] << 20);
+                float4 P = M.pl[x], Q = M.pl[y];
+                float sbx = M.psb[x], sby = M.psb[y];
+                // n0 = a_x cross a_y, n1 = a_y cross a_h, n2 = a_h cross a_x
+                float n00 = P.y * Q.z - P.z * Q.y, n01 = P.z * Q.x - P.x * Q.z, n02 = P.x * Q.y - P.y * Q.x;
+                float n10 = Q.y * az - Q.z * ay, n11 = Q.z * ax - Q.x * az, n12 = Q.x * ay - Q.y * ax;
+                float n20 = ay * P.z - az * P.y, n21 = az * P.x - ax * P.z, n22 = ax * P.y - ay * P.x;
+                float det = fmaf(ax, n00, fmaf(ay, n01, az * n02));
+                float inv = 1.0f / det;
+                y0[s] = (b * n00 + P.w * n10 + Q.w * n20) * inv;
+                y1[s] = (b * n01 + P.w * n11 + Q.w * n21) * inv;
+                y2[s] = (b * n02 + P.w * n12 + Q.w * n22) * inv;
+                float e = (sbh * (fabsf(n00) + fabsf(n01) + fabsf(n02)) + sbx * (fabsf(n10) + fabsf(n11) + fabsf(n12)) +
+                           sby * (fabsf(n20) + fabsf(n21) + fabsf(n22))) * fabsf(inv);
+                ev[s] = e + fabsf(y0[s]) + fabsf(y1[s]) + fabsf(y2[s]);
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) alive[s] = (alive[s] & ~R[s]) | ballot(isnew[s]);
+        if (ln == 0) {
+            M.pl[h] = make_float4(ax, ay, az, b);
+            M.psb[h] = sbh;
+            M.pcode[h] = hcode;
+        }
+        np = (int)h + 1;
+        wave_sync();
+        return kChanged;
+    }
+
+    __device__ int clip(float ax, float ay, float az, float b, float sbh, int32_t hcode) {
+        uint64_t R[VPL];
+        const int mode = A.precision == 2 ? 1 : 0;
+        classify(ax, ay, az, b, sbh, hcode, mode, R);
+        bool ok;
+        int r = apply(R, ax, ay, az, b, sbh, hcode, &ok);
+        if (ok) return r;
+        // inconsistent boundary: take doubtful signs as inside and retry once
+        flags |= kFlagUncertain;
+        classify(ax, ay, az, b, sbh, hcode, 2, R);
+        r = apply(R, ax, ay, az, b, sbh, hcode, &ok);
+        return ok ? r : kNone;
+    }
+
+    // Drop planes no vertex uses (supplementary Sec. A, "Garbage collection").
+    __device__ void gc() {
+        for (int q = ln; q < CAP; q += 64) M.key[q] = 0;
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < VPL; ++s)
+            if ((alive[s] >> ln) & 1) {
+                M.key[f10(vt[s], 0)] = 1;
+                M.key[f10(vt[s], 1)] = 1;
+                M.key[f10(vt[s], 2)] = 1;
+            }
+        wave_sync();
+        float4 pl[VPL];
+        float sb[VPL];
+        int32_t pc[VPL];
+        uint32_t dst[VPL];
+        bool used[VPL];
+        uint32_t cnt = 0;
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) {
+            int q = s * 64 + ln;
+            used[s] = q < np && M.key[q] != 0;
+            uint64_t u = ballot(used[s]);
+            dst[s] = cnt + mbcnt(u);
+            cnt += popc(u);
+            if (used[s]) {
+                pl[s] = M.pl[q];
+                sb[s] = M.psb[q];
+                pc[s] = M.pcode[q];
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) {
+            int q = s * 64 + ln;
+            if (used[s]) {
+                M.pl[dst[s]] = pl[s];
+                M.psb[dst[s]] = sb[s];
+                M.pcode[dst[s]] = pc[s];
+                M.key[q] = (int32_t)dst[s];
+            }
+        }
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < VPL; ++s)
+            if ((alive[s] >> ln) & 1)
+                vt[s] = (uint32_t)M.key[f10(vt[s], 0)] | ((uint32_t)M.key[f10(vt[s], 1)] << 10) |
+                        ((uint32_t)M.key[f10(vt[s], 2)] << 20);
+        np = (int)cnt;
+        wave_sync();
+    }
+
+    // ------------------------------------------------------------ traversal
+    // Tests child `s` of internal node `node` against the current cell.
+    __device__ void node_test(const NodeChild& c, float* key, bool* cull, float* delta) const {
+        float blx = c.lo[0] - px, bly = c.lo[1] - py, blz = c.lo[2] - pz;
+        float bhx = c.hi[0] - px, bhy = c.hi[1] - py, bhz = c.hi[2] - pz;
+        float dx = fmaxf(fmaxf(blx, -bhx), 0.f), dy = fmaxf(fmaxf(bly, -bhy), 0.f), dz = fmaxf(fmaxf(blz, -bhz), 0.f);
+        float d = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        float dw = pw - c.wmax;
+        float lb, err;
+        if (dw >= 0.f) {
+            lb = 0.5f * d;
+            err = 0.5f * d;
+        } else if (d > 0.f) {
+            lb = 0.5f * d + 0.5f * dw / d;
+            err = 0.5f * d - 0.5f * dw / d;
+        } else {
+            lb = -INFINITY;
+            err = 0.f;
+        }
+        float rb2;
+        if (A.culling == 2) {
+            rb2 = riso2;
+        } else {
+            float tx = bhx >= 0.f ? (blx < 0.f ? fmaxf(hx2, lx2) : hx2) : lx2;
+            float ty = bhy >= 0.f ? (bly < 0.f ? fmaxf(hy2, ly2) : hy2) : ly2;
+            float tz = bhz >= 0.f ? (blz < 0.f ? fmaxf(hz2, lz2) : hz2) : lz2;
+            rb2 = tx + ty + tz;
+        }
+        float rb = sqrtf(rb2);
+        // lower bound made safe against FP32 rounding of its terms
+        float lbs = lb - 16.f * kU * err;
+        *key = lbs;
+        *cull = lbs > rb * (1.f + 16.f * kU);
+        *delta = lbs - rb;
+    }
+
+    __device__ void push(uint32_t e, float k) {
+        const int slot = qn >> 6, l = qn & 63;
+#pragma unroll
+        for (int s = 0; s < VPL; ++s)
+            if (s == slot && (int)ln == l) {
+                qe[s] = e;
+                qk[s] = k;
+            }
+        ++qn;
+    }
+
+    // Removes and returns the entry with the smallest key (best-first), or
+    // the last pushed one (depth-first).
+    __device__ void pop(uint32_t* e, float* k) {
+        int S, L;
+        if (A.traversal == 2) {
+            S = (qn - 1) >> 6;
+            L = (qn - 1) & 63;
+        } else {
+            float bk = INFINITY;
+            int bs = 0;
+#pragma unroll
+            for (int s = 0; s < VPL; ++s) {
+                int idx = s * 64 + (int)ln;
+                if (idx < qn && qk[s] < bk) {
+                    bk = qk[s];
+                    bs = s;
+                }
+            }
+            float m = wmin(bk);
+            uint64_t msk = ballot(bk == m && (int)ln < qn);
+            L = msk ? lowest(msk) : 0;
+            S = rdl(bs, L);
+        }
+        uint32_t ee = 0;
+        float kk = 0.f;
+#pragma unroll
+        for (int s = 0; s < VPL; ++s)
+            if (s == S) {
+                ee = rdl(qe[s], L);
+                kk = rdl(qk[s], L);
+            }
+        const int last = qn - 1, ls = last >> 6, ll = last & 63;
+        uint32_t le = 0;
+        float lk = 0.f;
+#pragma unroll
+        for (int s = 0; s < VPL; ++s)
+            if (s == ls) {
+                le = rdl(qe[s], ll);
+                lk = rdl(qk[s], ll);
+            }
+#pragma unroll
+        for (int s = 0; s < VPL; ++s)
+            if (s == S && (int)ln == L) {
+                qe[s] = le;
+                qk[s] = lk;
+            }
+        --qn;
+        *e = ee;
+        *k = kk;
+    }
+
+    // Clips by the candidate sites of one leaf; nearest plane first.
+    __device__ int leaf(uint32_t ref) {
+        const uint32_t first = leaf_first(ref), count = leaf_count(ref);
+        float ax = 0.f, ay = 0.f, az = 0.f, a2 = 0.f, b = 0.f, dw = 0.f, key = INFINITY;
+        bool cand = false;
+        if (ln < count) {
+            uint32_t j = first + ln;
+            float4 q = A.pts[j];
+            if (j != self && q.w != -INFINITY) {
+                ax = q.x - px; ay = q.y - py; az = q.z - pz;
+                a2 = fmaf(ax, ax, fmaf(ay, ay, az * az));
+                dw = pw - q.w;
+                b = 0.5f * (a2 + dw);
+                cand = a2 > 0.f;
+                key = b * rsqrtf(a2);
+            }
+        }
+        auto keep = [&](bool c) -> bool {
+            if (!c) return false;
+            float r2 = radius2_toward(ax, ay, az);
+            float t = b - 4.f * kU * (2.f * a2 + fabsf(dw) + r2);
+            return !(t > 0.f && t * t > a2 * r2);
+        };
+        uint64_t mask = ballot(keep(cand));
+        while (mask) {
+            int L;
+            if (A.traversal == 2) {
+                L = lowest(mask);
+            } else {
+                float kk = ((mask >> ln) & 1) ? key : INFINITY;
+                float m = wmin(kk);
+                uint64_t mm = ballot(kk == m) & mask;
+                L = lowest(mm ? mm : mask);
+            }
+            mask &= ~(1ull << L);
+            float hx = rdl(ax, L), hy = rdl(ay, L), hz = rdl(az, L), hb = rdl(b, L);
+            float sb = 0.5f * (rdl(a2, L) + fabsf(rdl(dw, L)));
+            int r = clip(hx, hy, hz, hb, sb, (int32_t)(first + (uint32_t)L));
+            if (r == kEmptied || r == kOverflow) return r;
+            if (r == kChanged) {
+                update_bounds();
+                mask &= ballot(keep(true));
+            }
+        }
+        return kNone;
+    }
+
+    __device__ void load_child(uint32_t node, int s, NodeChild* c) const {
+        const float4* src = reinterpret_cast<const float4*>(&A.nodes[node].c[s]);
+        float4 u = src[0], v = src[1];
+        c->lo[0] = u.x; c->lo[1] = u.y; c->lo[2] = u.z; c->wmax = u.w;
+        c->hi[0] = v.x; c->hi[1] = v.y; c->hi[2] = v.z; c->ref = __float_as_uint(v.w);
+    }
+
+    // Alg. 1.  Returns kNone when done, kEmptied or kOverflow.
+    __device__ int traverse() {
+        uint32_t cur = A.root;
+        bool have = true;
+        // every node is visited at most once in a valid tree; the bound only
+        // guarantees termination if the tree were ever malformed
+        int64_t budget = 4 * A.n + 1024;
+        for (;;) {
+            while (have && !ref_is_leaf(cur)) {
+                if (--budget < 0) return kOverflow;
+                const uint32_t node = cur;
+                float key = 0.f, delta = 0.f;
+                bool cull = true;
+                uint32_t ref = 0;
+                if (ln < 2) {
+                    NodeChild c;
+                    load_child(node, (int)ln, &c);
+                    node_test(c, &key, &cull, &delta);
+                    ref = c.ref;
+                }
+                const bool c0 = rdl((int)cull, 0) != 0, c1 = rdl((int)cull, 1) != 0;
+                if (c0 && c1) {
+                    have = false;
+                    break;
+                }
+                const float d0 = rdl(delta, 0), d1 = rdl(delta, 1);
+                int near;
+                if (A.traversal == 2) near = c0 ? 1 : 0;
+                else near = c1 ? 0 : (c0 ? 1 : (d0 <= d1 ? 0 : 1));
+                const int far = 1 - near;
+                if (!(far ? c1 : c0)) {
+                    if (qn >= CAP) return kOverflow;
+                    push((node << 1) | (uint32_t)far, rdl(key, far));
+                }
+                cur = rdl(ref, near);
+            }
+            if (have) {
+                int r = leaf(cur);
+                if (r != kNone) return r;
+            }
+            have = false;
+            while (qn > 0) {
+                if (--budget < 0) return kOverflow;
+                uint32_t e;
+                float k;
+                pop(&e, &k);
+                if (A.traversal != 2 && k > sqrtf(rmax2) * (1.f + 16.f * kU)) {
+                    qn = 0;  // every key left is at least k: nothing can cut the cell
+                    break;
+                }
+                float key = 0.f, delta = 0.f;
+                bool cull = true;
+                uint32_t ref = 0;
+                if (ln == 0) {
+                    NodeChild c;
+                    load_child(e >> 1, (int)(e & 1), &c);
+                    node_test(c, &key, &cull, &delta);
+                    ref = c.ref;
+                }
+                if (!rdl((int)cull, 0)) {
+                    cur = rdl(ref, 0);
+                    have = true;
+                    break;
+                }
+            }
+            if (!have) return kNone;
+        }
+    }
+
+    // ------------------------------------------------------------ output
+    __device__ void finalize(uint32_t slot, uint32_t orig) {
+        gc();
+        const int F = np;
+        // facet order: ascending output code (box faces -6..-1, then original site ids)
+        for (int q = ln; q < F; q += 64) {
+            int32_t c = M.pcode[q];
+            M.key[q] = c >= 0 ? (int32_t)A.order[c] : c;
+        }
+        wave_sync();
+        for (int q = ln; q < F; q += 64) {
+            int32_t mine = M.key[q];
+            uint32_t r = 0;
+            for (int t = 0; t < F; ++t) r += M.key[t] < mine ? 1u : 0u;
+            M.ta[q] = r;
+            M.tb[q] = 0;
+            M.edge[q] = 0xFFFFFFFFu;
+        }
+        wave_sync();
+        const Stage& st = A.stage;
+        int32_t* codes = st.code + (int64_t)slot * st.cap;
+        for (int q = ln; q < F; q += 64) codes[M.ta[q]] = M.key[q];
+        // vertex renumbering 0..nv-1
+        uint32_t vid[VPL];
+        uint32_t nv = 0;
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) {
+            vid[s] = nv + mbcnt(alive[s]);
+            nv += popc(alive[s]);
+            if ((alive[s] >> ln) & 1) M.sor[s * 64 + ln] = vid[s];
+        }
+        wave_sync();
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) {
+            if ((alive[s] >> ln) & 1) {
+                uint32_t t0 = M.ta[f10(vt[s], 0)], t1 = M.ta[f10(vt[s], 1)], t2 = M.ta[f10(vt[s], 2)];
+                uint32_t a0 = M.sor[f10(va[s], 0)], a1 = M.sor[f10(va[s], 1)], a2 = M.sor[f10(va[s], 2)];
+                M.vtri[vid[s]] = t0 | (t1 << 10) | (t2 << 20);
+                M.vadj[vid[s]] = a0 | (a1 << 10) | (a2 << 20);
+                M.vpos[vid[s]] = make_float4(y0[s], y1[s], y2[s], 0.f);
+                atomicAdd(&M.tb[t0], 1u);
+                atomicAdd(&M.tb[t1], 1u);
+                atomicAdd(&M.tb[t2], 1u);
+                atomicMin(&M.edge[t0], vid[s]);
+                atomicMin(&M.edge[t1], vid[s]);
+                atomicMin(&M.edge[t2], vid[s]);
+            }
+        }
+        wave_sync();
+        // facet sizes, offsets and vertex rings (CCW seen from outside)
+        uint16_t* fs = st.fsize + (int64_t)slot * st.cap;
+        uint16_t* fvp = st.fv + (int64_t)slot * 3 * st.cap;
+        uint32_t carry = 0;
+        bool bad = false;
+        for (int q0 = 0; q0 < F; q0 += 64) {
+            int q = q0 + (int)ln;
+            uint32_t sz = q < F ? M.tb[q] : 0u;
+            uint32_t x = sz;
+            for (int o = 1; o < 64; o <<= 1) {
+                uint32_t y = __shfl_up(x, o);
+                if ((int)ln >= o) x += y;
+            }
+            if (q < F) {
+                fs[q] = (uint16_t)sz;
+                uint32_t base = carry + x - sz;
+                uint32_t start = M.edge[q], v = start, t = 0;
+                do {
+                    fvp[base + t] = (uint16_t)v;
+                    ++t;
+                    uint32_t tri = M.vtri[v], adj = M.vadj[v];
+                    int k = f10(tri, 0) == (uint32_t)q ? 0 : (f10(tri, 1) == (uint32_t)q ? 1 : 2);
+                    v = f10(adj, (k + 1) % 3);
+                } while (v != start && t < sz);
+                bad |= (v != start) || (t != sz);
+            }
+            carry += (uint32_t)__shfl(x, 63);
+        }
+        if (ballot(bad)) flags |= kFlagUncertain;
+        // positions (global) and sorted facet triples; volume and centroid
+        // from the tetrahedra (ref, anchor_f, v, next_f(v))
+        const float4 ref = M.vpos[0];
+        float4* vout = st.vert + (int64_t)slot * st.cap;
+        float vol6 = 0.f, mx = 0.f, my = 0.f, mz = 0.f;
+        for (uint32_t v = ln; v < nv; v += 64) {
+            float4 P = M.vpos[v];
+            uint32_t tri = M.vtri[v], adj = M.vadj[v];
+            uint32_t t0 = f10(tri, 0), t1 = f10(tri, 1), t2 = f10(tri, 2), tmp;
+            if (t0 > t1) { tmp = t0; t0 = t1; t1 = tmp; }
+            if (t1 > t2) { tmp = t1; t1 = t2; t2 = tmp; }
+            if (t0 > t1) { tmp = t0; t0 = t1; t1 = tmp; }
+            vout[v] = make_float4(px + P.x, py + P.y, pz + P.z, __uint_as_float(t0 | (t1 << 10) | (t2 << 20)));
+            float bx = P.x - ref.x, by = P.y - ref.y, bz = P.z - ref.z;
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                uint32_t f = f10(tri, k);
+                uint32_t an = M.edge[f];
+                uint32_t nx = f10(adj, (k + 1) % 3);
+                if (an == v || nx == an) continue;
+                float4 Q = M.vpos[an], N = M.vpos[nx];
+                float qx = Q.x - ref.x, qy = Q.y - ref.y, qz = Q.z - ref.z;
+                float nxx = N.x - ref.x, nyy = N.y - ref.y, nzz = N.z - ref.z;
+                // det(anchor, v, next) relative to ref
+                float cx = by * nzz - bz * nyy, cy = bz * nxx - bx * nzz, cz = bx * nyy - by * nxx;
+                float det = fmaf(qx, cx, fmaf(qy, cy, qz * cz));
+                vol6 += det;
+                mx += det * (qx + bx + nxx);
+                my += det * (qy + by + nyy);
+                mz += det * (qz + bz + nzz);
+            }
+        }
+        vol6 = wsum(vol6);
+        mx = wsum(mx);
+        my = wsum(my);
+        mz = wsum(mz);
+        uint32_t nbox = 0;
+        for (int q = ln; q < F; q += 64) nbox += M.key[q] < 0 ? 1u : 0u;
+        nbox = wsum_u(nbox);
+        if (ln == 0) {
+            A.cnt_v[orig] = nv;
+            A.cnt_f[orig] = (uint32_t)F;
+            A.cnt_n[orig] = (uint32_t)F - nbox;
+            A.vol[orig] = vol6 / 6.f;
+            float inv = vol6 != 0.f ? 0.25f / vol6 : 0.f;
+            A.cen[3 * orig] = px + ref.x + mx * inv;
+            A.cen[3 * orig + 1] = py + ref.y + my * inv;
+            A.cen[3 * orig + 2] = pz + ref.z + mz * inv;
+            A.flags[orig] = (uint8_t)flags;
+            A.loc[self] = make_loc((uint32_t)A.tier, slot);
+        }
+    }
+
+    __device__ void write_empty(uint32_t orig, uint32_t extra) {
+        if (ln == 0) {
+            A.cnt_v[orig] = 0;
+            A.cnt_f[orig] = 0;
+            A.cnt_n[orig] = 0;
+            A.vol[orig] = 0.f;
+            A.cen[3 * orig] = px;
+            A.cen[3 * orig + 1] = py;
+            A.cen[3 * orig + 2] = pz;
+            A.flags[orig] = (uint8_t)(flags | kFlagEmpty | extra);
+            A.loc[self] = make_loc((uint32_t)A.tier, 0);
+        }
+    }
+};
+
+template <int VPL, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_clip(ClipArgs A) {
+    __shared__ WaveMem<VPL> mem[WAVES];
+    WaveMem<VPL>& M = mem[threadIdx.x >> 6];
+    Cell<VPL> C(M, A);
+    const uint32_t count = A.list ? *A.list_count : (uint32_t)A.n;
+    unsigned long long st_empty = 0, st_large = 0, st_unc = 0, st_fail = 0, st_fp64 = 0;
+    for (;;) {
+        uint32_t c = 0;
+        if (C.ln == 0) c = atomicAdd(A.work_counter, 1u);
+        c = (uint32_t)__builtin_amdgcn_readfirstlane((int)c);
+        if (c >= count) break;
+        const uint32_t k = A.list ? A.list[c] : c;
+        const uint32_t slot = A.list ? c : k;
+        const uint32_t orig = A.order[k];
+        if (!C.init(k)) {
+            C.write_empty(orig, 0);
+            ++st_empty;
+            continue;
+        }
+        if (A.tier > 0) C.flags |= kFlagLarge;
+        int r = C.traverse();
+        if (r == kOverflow) {
+            if (A.next_list) {
+                if (C.ln == 0) A.next_list[atomicAdd(A.next_count, 1u)] = k;
+            } else {
+                C.write_empty(orig, kFlagFailed);
+                ++st_fail;
+                ++st_empty;
+            }
+            continue;
+        }
+        if (r == kEmptied) {
+            C.write_empty(orig, 0);
+            ++st_empty;
+        } else {
+            C.finalize(slot, orig);
+        }
+        st_large += (C.flags & kFlagLarge) ? 1 : 0;
+        st_unc += (C.flags & kFlagUncertain) ? 1 : 0;
+        st_fp64 += (C.flags & kFlagFP64) ? 1 : 0;
+    }
+    if (C.ln == 0) {
+        if (st_empty) atomicAdd(&A.stats[kStatEmpty], st_empty);
+        if (st_large) atomicAdd(&A.stats[kStatLarge], st_large);
+        if (st_unc) atomicAdd(&A.stats[kStatUncertain], st_unc);
+        if (st_fail) atomicAdd(&A.stats[kStatFailed], st_fail);
+        if (st_fp64) atomicAdd(&A.stats[kStatFP64], st_fp64);
+    }
+}
+
+}  // namespace
+
+int clip_grid_waves(int tier, int num_cu) {
+    int per_cu = 0;
+    hipError_t e;
+    if (tier == 0) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip<1, 4>, 256, 0);
+        per_cu *= 4;
+    } else if (tier == 1) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip<4, 2>, 128, 0);
+        per_cu *= 2;
+    } else {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip<16, 1>, 64, 0);
+    }
+    if (e != hipSuccess || per_cu < 1) per_cu = 4;
+    return per_cu * num_cu;
+}
+
+hipError_t launch_clip(const ClipArgs& a, int grid_waves, hipStream_t s) {
+    switch (a.tier) {
+        case 0: {
+            int blocks = (grid_waves + 3) / 4;
+            hipLaunchKernelGGL((k_clip<1, 4>), dim3(blocks), dim3(256), 0, s, a);
+            break;
+        }
+        case 1: {
+            int blocks = (grid_waves + 1) / 2;
+            hipLaunchKernelGGL((k_clip<4, 2>), dim3(blocks), dim3(128), 0, s, a);
+            break;
+        }
+        default:
+            hipLaunchKernelGGL((k_clip<16, 1>), dim3(grid_waves), dim3(64), 0, s, a);
+            break;
+    }
+    return hipGetLastError();
+}
+
+}  // namespace vd

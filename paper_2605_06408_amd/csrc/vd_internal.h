@@ -1,0 +1,152 @@
+// Internal declarations shared by the libvd translation units (not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace vd {
+
+// ---------------------------------------------------------------- limits
+
+constexpr int kMaxLeaf = 64;                 // leaf refs store count-1 in 6 bits
+constexpr int64_t kMaxSites = int64_t(1) << 25;  // leaf refs store `first` in 25 bits
+constexpr int kDefaultLeaf = 16;
+
+// ---------------------------------------------------------------- BVH
+
+// One child of a binary BVH node: its box, the largest weight of the sites
+// below it (the power-diagram augmentation of paper Sec. 4.3) and a
+// reference.  A reference with bit 31 set is a leaf: bits 0..24 hold the
+// first site (Morton order) and bits 25..30 the site count minus one;
+// otherwise it is the index of an internal node.  Each internal node holds
+// both children's records side by side (64 bytes) so one visit reads one
+// contiguous block.
+struct __align__(16) NodeChild {
+    float lo[3];
+    float wmax;
+    float hi[3];
+    uint32_t ref;
+};
+struct __align__(16) Node {
+    NodeChild c[2];
+};
+
+constexpr uint32_t kLeafBit = 0x80000000u;
+__host__ __device__ inline uint32_t leaf_ref(uint32_t first, uint32_t count) {
+    return kLeafBit | ((count - 1u) << 25) | first;
+}
+__host__ __device__ inline bool ref_is_leaf(uint32_t r) { return (r & kLeafBit) != 0; }
+__host__ __device__ inline uint32_t leaf_first(uint32_t r) { return r & 0x1FFFFFFu; }
+__host__ __device__ inline uint32_t leaf_count(uint32_t r) { return ((r >> 25) & 63u) + 1u; }
+
+// ---------------------------------------------------------------- staging
+
+// Finished cells are written to fixed-capacity slots before the CSR pass.
+// Capacity `cap` = vertices = planes per cell; facet-vertex lists hold 3 cap.
+//   vert[slot*cap + v]   : global position xyz, .w = the vertex's three facet
+//                          ranks (ascending, 10 bits each) as raw bits
+//   code[slot*cap + f]   : facet codes in ascending order (site ids, box -1..-6)
+//   fsize[slot*cap + f]  : vertices of facet f
+//   fv[slot*3cap + t]    : cell-local vertex indices of all facets, concatenated
+struct Stage {
+    int cap;
+    float4* vert;
+    int32_t* code;
+    uint16_t* fsize;
+    uint16_t* fv;
+};
+
+// Location of a cell's staged record: tier in bits 30..31, slot below.
+__host__ __device__ inline uint32_t make_loc(uint32_t tier, uint32_t slot) { return (tier << 30) | slot; }
+
+// Per-cell flag bits (mirror vd.h)
+constexpr uint32_t kFlagEmpty = 1u, kFlagFP64 = 2u, kFlagLarge = 4u, kFlagUncertain = 8u, kFlagFailed = 16u;
+
+// Build statistics accumulated by the clip kernels (device, uint64 each).
+enum StatIndex { kStatEmpty = 0, kStatLarge, kStatUncertain, kStatFailed, kStatFP64, kStatCount };
+
+struct ClipArgs {
+    const float4* pts;        // sites in Morton order: x, y, z, w (w = -inf: coincident loser)
+    const uint32_t* order;    // Morton position -> original index
+    const Node* nodes;        // internal nodes (n-1)
+    uint32_t root;            // root reference
+    const float* bbox;        // device [6]: lo.xyz, hi.xyz
+    int64_t n;
+    int leaf_size;
+    int culling;              // 1 directional, 2 isotropic
+    int traversal;            // 1 best-first, 2 depth-first
+    int precision;            // 1 fp32, 2 mixed
+    int tier;                 // 0, 1, 2
+    // work: cells c in [0, count) are list[c] (or c itself when list == null)
+    uint32_t* work_counter;
+    const uint32_t* list;
+    const uint32_t* list_count;   // device count (list != null), else count = n
+    uint32_t* next_list;      // escalation list for the next tier (null: last tier)
+    uint32_t* next_count;
+    Stage stage;
+    uint32_t* loc;            // [n] by Morton position
+    uint32_t* cnt_v;          // [n] by original index
+    uint32_t* cnt_f;
+    uint32_t* cnt_n;
+    float* vol;               // [n] by original index
+    float* cen;               // [3n]
+    uint8_t* flags;           // [n]
+    unsigned long long* stats;  // [kStatCount]
+};
+
+struct WriteArgs {
+    int64_t n;
+    const uint32_t* inv;      // original index -> Morton position
+    const uint32_t* loc;
+    Stage stage[3];
+    const uint32_t* cnt_v;
+    const uint32_t* cnt_f;
+    const uint32_t* cnt_n;
+    const int64_t* off_v;
+    const int64_t* off_f;
+    const int64_t* off_n;
+    int32_t* nbr;
+    int32_t* facet_nbr;
+    int64_t* fv_off;
+    int32_t* fv;
+    float* vert;
+    int32_t* vert_planes;
+};
+
+// ---------------------------------------------------------------- launches
+// (host wrappers; each returns the hipError_t of its launch)
+
+hipError_t launch_pack(const float* xyz, const float* w, int64_t n, float4* pts, uint32_t* err, hipStream_t s);
+hipError_t launch_bbox(const float4* pts, int64_t n, float* partial, int nblk_max, float* bbox, uint32_t* err,
+                       hipStream_t s);
+hipError_t launch_check_bbox(float* bbox, uint32_t* err, hipStream_t s);
+hipError_t launch_morton(const float4* pts, int64_t n, const float* bbox, uint64_t* keys, uint32_t* vals,
+                         hipStream_t s);
+// LSD radix sort of 64-bit keys with 32-bit values over `bits` low bits.
+// tmp buffers: same sizes; hist: radix_hist_size(n) uint32.
+size_t radix_hist_size(int64_t n);
+hipError_t radix_sort(uint64_t* keys, uint32_t* vals, uint64_t* keys_tmp, uint32_t* vals_tmp, int64_t n, int bits,
+                      uint32_t* hist, uint32_t* scan_tmp, hipStream_t s, bool* result_in_tmp);
+hipError_t launch_gather(const float4* pts, const uint32_t* order, int64_t n, float4* spts, uint32_t* inv,
+                         hipStream_t s);
+hipError_t launch_losers(float4* spts, const uint64_t* keys, const uint32_t* order, int64_t n, uint8_t* mark,
+                         hipStream_t s);
+hipError_t launch_karras(const uint64_t* keys, int64_t n, int2* child, int* parent_int, int* parent_leaf, int2* range,
+                         hipStream_t s);
+hipError_t launch_bounds(const float4* spts, int64_t n, const int2* child, const int* parent_int,
+                         const int* parent_leaf, const int2* range, uint32_t* counters, Node* nodes, int leaf_size,
+                         hipStream_t s);
+
+// Exclusive scan of uint32 counts into int64 offsets [n+1] (out[n] = total).
+size_t scan_tmp_size(int64_t n);
+hipError_t scan_counts(const uint32_t* in, int64_t n, int64_t* out, int64_t* tmp, hipStream_t s);
+// Exclusive scan of uint32 -> uint32 (for radix histograms).
+hipError_t scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* tmp, hipStream_t s);
+
+int clip_grid_waves(int tier, int num_cu);
+hipError_t launch_clip(const ClipArgs& a, int grid_waves, hipStream_t s);
+hipError_t launch_set_i64(int64_t* dst, int64_t value, hipStream_t s);
+hipError_t launch_write(const WriteArgs& a, hipStream_t s);
+
+}  // namespace vd

@@ -1,0 +1,211 @@
+"""GPU path vs the CPU oracle: whole diagrams at sizes the oracle finishes in
+seconds (several BVH levels, every tier of leaf and a ragged tail), edge
+cases, option equivalences and exact metamorphic relations.  All calls go
+through the C ABI (ctypes binding)."""
+import itertools
+
+import numpy as np
+import pytest
+
+from paper_2605_06408_amd import workloads as wl
+
+from .parity import assert_parity, compare, gpu_build, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+TAU32 = 1e-5  # certification margin for the FP32 path (see parity.py)
+
+
+def _full_parity(oracle_mod, xyz, w, box, tau=TAU32, min_frac=0.9, **kw):
+    d = gpu_build(xyz, w, box, **kw)
+    assert d.sizes["n_failed"] == 0
+    g = to_numpy(d)
+    o = oracle_mod.cells(xyz, w, box)
+    rep = compare(g, o, tau=tau)
+    rep["sizes"] = d.sizes
+    assert_parity(rep, min_frac)
+    return d, g, o, rep
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_uniform_10k_voronoi(oracle_mod, seed):
+    xyz, w, box = wl.make("uniform_10k", seed)
+    _full_parity(oracle_mod, xyz, w, box)
+
+
+def test_power_uniform_small(oracle_mod):
+    xyz, w, box = wl.power_uniform(20000, 3)
+    _, g, _, rep = _full_parity(oracle_mod, xyz, w, box)
+    assert rep["empty"] > 0
+
+
+def test_power_paper_weights(oracle_mod):
+    # the paper's own weight law: w ~ N(0, (d_nn^2 / 3)^2)
+    from scipy.spatial import cKDTree
+    xyz, _, box = wl.uniform(15000, 4)
+    d, _ = cKDTree(xyz).query(xyz, k=2)
+    dnn = float(np.median(d[:, 1]))
+    w = np.random.default_rng(4).normal(0.0, dnn * dnn / 3.0, size=len(xyz)).astype(np.float32)
+    _full_parity(oracle_mod, xyz, w, box)
+
+
+def test_clustered_small(oracle_mod):
+    xyz, w, box = wl.clustered(20000, 5)
+    _full_parity(oracle_mod, xyz, w, box, min_frac=0.85)
+
+
+def test_surface_small(oracle_mod):
+    xyz, w, box = wl.surface(20000, 6)
+    _full_parity(oracle_mod, xyz, w, box, min_frac=0.85)
+
+
+def test_power_clustered_small(oracle_mod):
+    xyz, w, box = wl.power_clustered(20000, 7)
+    _full_parity(oracle_mod, xyz, w, box, min_frac=0.85)
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 15, 16, 17, 63, 64, 65, 1000, 4097])
+def test_ragged_sizes(oracle_mod, n):
+    xyz, w, box = wl.uniform(n, 100 + n)
+    _full_parity(oracle_mod, xyz, w, box, min_frac=0.8)
+
+
+def test_single_site_is_box():
+    d = gpu_build(np.array([[0.2, 0.7, 2.1]], np.float32), None, [-1.0, 0.5, 2.0, 3.0, 1.5, 2.25])
+    assert float(d.vol[0]) == pytest.approx(1.0, rel=1e-6)
+    np.testing.assert_allclose(d.centroid[0].cpu().numpy(), [1.0, 1.0, 2.125], rtol=1e-6)
+    assert d.facet_nbr.cpu().tolist() == [-6, -5, -4, -3, -2, -1]
+    assert d.sizes["n_vert"] == 8 and d.sizes["n_nbr"] == 0
+
+
+@pytest.mark.parametrize("w0,w1", [(0.0, 0.0), (0.1, 0.0), (0.0, 0.3), (0.7, 0.0), (0.0, 0.7)])
+def test_two_sites_axis(oracle_mod, w0, w1):
+    xyz = np.array([[0.25, 0.5, 0.5], [0.75, 0.5, 0.5]], np.float32)
+    w = np.array([w0, w1], np.float32)
+    _full_parity(oracle_mod, xyz, w, wl.UNIT_BOX, min_frac=1.0)
+
+
+def test_all_sites_coincident():
+    xyz = np.tile(np.array([[0.3, 0.6, 0.2]], np.float32), (7, 1))
+    d = gpu_build(xyz, None, wl.UNIT_BOX)
+    fl = d.flags.cpu().numpy()
+    assert not fl[0] & 1 and np.all(fl[1:] & 1)
+    assert float(d.vol[0]) == pytest.approx(1.0, rel=1e-6)
+    w = np.array([0, 0, 0.5, 0.5, 0, 0, 0], np.float32)  # the heaviest, lowest index wins
+    d = gpu_build(xyz, w, wl.UNIT_BOX)
+    fl = d.flags.cpu().numpy()
+    assert [int(x & 1) for x in fl] == [1, 1, 0, 1, 1, 1, 1]
+
+
+def test_coincident_pairs_in_random_data(oracle_mod):
+    xyz, _, box = wl.uniform(3000, 12)
+    rng = np.random.default_rng(12)
+    src = rng.choice(3000, 40, replace=False)
+    dst = rng.choice(3000, 40, replace=False)
+    xyz[dst] = xyz[src]
+    w = (rng.integers(0, 4, size=3000) * 1e-6).astype(np.float32)
+    _full_parity(oracle_mod, xyz, w, box, min_frac=0.8)
+
+
+def test_sites_outside_box(oracle_mod):
+    rng = np.random.default_rng(13)
+    xyz = (rng.random((2000, 3)) * 1.6 - 0.3).astype(np.float32)
+    w = (rng.random(2000) * 1e-3).astype(np.float32)
+    _full_parity(oracle_mod, xyz, w, np.array([0.0, 0.1, 0.0, 1.0, 0.9, 1.2]), min_frac=0.8)
+
+
+def test_default_box_is_site_aabb(oracle_mod):
+    xyz, _, _ = wl.uniform(3000, 14)
+    d = gpu_build(xyz, None, None)
+    o = oracle_mod.cells(xyz, None, None)
+    rep = compare(to_numpy(d), o)
+    assert_parity(rep)
+
+
+def test_lattice_geometry():
+    m = 8
+    g = (np.arange(m) + 0.5) / m
+    xyz = np.array(list(itertools.product(g, g, g)), np.float32)
+    d = gpu_build(xyz, None, wl.UNIT_BOX)
+    np.testing.assert_allclose(d.vol.cpu().numpy(), 1.0 / m ** 3, rtol=1e-5)
+    np.testing.assert_allclose(d.centroid.cpu().numpy(), xyz, atol=1e-6)
+
+
+def test_jittered_lattice_near_unit_cubes(oracle_mod):
+    m = 10
+    rng = np.random.default_rng(3)
+    g = np.arange(m) + 0.5
+    xyz = (np.array(list(itertools.product(g, g, g))) + rng.uniform(-0.02, 0.02, size=(m ** 3, 3))).astype(np.float32)
+    box = np.array([0.0, 0.0, 0.0, m, m, m], float)
+    d, gnp, o, rep = _full_parity(oracle_mod, xyz, None, box, min_frac=0.5)
+    vol = gnp["vol"]
+    assert vol.sum() == pytest.approx(m ** 3, rel=1e-5)
+    assert np.all(np.abs(vol - 1.0) < 0.15)
+
+
+# ------------------------------------------------------------ options
+
+@pytest.mark.parametrize("leaf", [1, 4, 32, 64])
+def test_leaf_sizes_agree(oracle_mod, leaf):
+    xyz, w, box = wl.power_clustered(8000, 21)
+    _full_parity(oracle_mod, xyz, w, box, min_frac=0.8, leaf_size=leaf)
+
+
+@pytest.mark.parametrize("kw", [dict(culling=2), dict(traversal=2), dict(precision=2)],
+                         ids=["isotropic", "depth_first", "mixed"])
+def test_ablation_switches_agree(oracle_mod, kw):
+    xyz, w, box = wl.clustered(8000, 22)
+    _full_parity(oracle_mod, xyz, w, box, min_frac=0.8, **kw)
+
+
+# ------------------------------------------------------------ metamorphic
+
+@pytest.mark.parametrize("k", [3, -2])
+def test_power_of_two_scaling_is_exact(k):
+    xyz, w, box = wl.power_uniform(5000, 8)
+    w = (w * 0.1).astype(np.float32)
+    s = np.float32(2.0 ** k)
+    a = to_numpy(gpu_build(xyz, w, box))
+    b = to_numpy(gpu_build(xyz * s, w * s * s, box * float(s)))
+    for key in ["nbr_off", "nbr", "facet_off", "facet_nbr", "fv_off", "fv", "vert_off", "vert_planes", "flags"]:
+        np.testing.assert_array_equal(a[key], b[key])
+    np.testing.assert_array_equal(a["vert"] * s, b["vert"])
+    np.testing.assert_array_equal(a["vol"] * s ** 3, b["vol"])
+
+
+def test_repeat_builds_identical():
+    xyz, w, box = wl.power_clustered(20000, 9)
+    a = to_numpy(gpu_build(xyz, w, box))
+    b = to_numpy(gpu_build(xyz, w, box))
+    for key in a:
+        np.testing.assert_array_equal(a[key], b[key])
+
+
+def test_partition_invariants_on_gpu():
+    xyz, w, box = wl.surface(50000, 15)
+    d = gpu_build(xyz, w, box)
+    g = to_numpy(d)
+    bvol = float(np.prod(box[3:] - box[:3]))
+    assert g["vol"].astype(np.float64).sum() == pytest.approx(bvol, rel=1e-5)
+    n = len(g["vol"])
+    rows = np.repeat(np.arange(n), np.diff(g["nbr_off"]))
+    fwd = set(zip(rows.tolist(), g["nbr"].tolist()))
+    assert all((j, i) in fwd for i, j in fwd)
+
+
+# ------------------------------------------------------------ errors
+
+def test_non_finite_input_rejected():
+    import paper_2605_06408_amd as vd
+    xyz, _, box = wl.uniform(100, 1)
+    xyz[7, 1] = np.nan
+    with pytest.raises(vd.VDError) as e:
+        gpu_build(xyz, None, box)
+    assert e.value.status == 1
+
+
+def test_bad_bbox_rejected():
+    import paper_2605_06408_amd as vd
+    xyz, _, _ = wl.uniform(100, 1)
+    with pytest.raises(vd.VDError):
+        gpu_build(xyz, None, [0, 0, 0, 1, 0, 1])

@@ -49,7 +49,7 @@ def test_planted_mistake_is_caught(name, tmp_path):
     subprocess.run(["g++", "-O1", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o",
                     str(pkg / "liboracle.so"), str(pkg / "vd_oracle.cpp")], check=True)
     code = ("import sys; sys.path.insert(0, %r); sys.path.insert(1, %r); import pytest; "
-            "sys.exit(pytest.main(['-q', '-x', '-p', 'no:cacheprovider', %r]))"
+            "sys.exit(pytest.main(['-q', '-x', '-p', 'no:cacheprovider', '--import-mode=append', %r]))"
             % (str(tmp_path), ROOT, os.path.join(ROOT, "tests", "test_oracle_pins.py")))
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=str(tmp_path),
                        timeout=600)
