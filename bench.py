@@ -1,0 +1,155 @@
+"""Throughput of the diagram construction on one MI355X.
+
+One step = one full vd_build + vd_write (LBVH build, traversal and clipping,
+prefix sums, CSR write-out of neighbours, facets, vertices, volumes and
+centroids) over the whole site set, with the sites already resident in HBM.
+Timing follows the paper's protocol (Sec. 5.2: warm-up runs, then the mean
+of timed runs), bracketed by device synchronisation.
+
+Prints one JSON line with the metric, the roofline of the dominant kernel
+(the 64-vertex traversal+clip kernel, timed by HIP events on the library's
+stream) and the CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "cells/sec at 1M and 20M sites (Voronoi, power); fwd+bwd cells/sec"
+
+# Nominal FP32 flops of one occurrence of each counted work unit (FMA = 2).
+# They price the arithmetic the method needs for that unit, not the
+# instructions this implementation happens to issue:
+#   classify     a.y - b over 3 components and a compare            3 FMA + 1 = 7
+#   new_vertex   three cross products (27), determinant (5), the
+#                three numerator components (15), reciprocal + scale (4)     = 51
+#   node_test    closest point (12), distance and weight bound (6),
+#                octant radius (8), two square roots + compare (6)           = 32
+#   site_test    difference (3), |a|^2 (5), b (2), octant radius (5),
+#                rounding slack and squared compare (10)                     = 25
+#   final_vertex three fan tetrahedra: cross (9), dot (5), moment (6) each   = 60
+FLOPS_PER_UNIT = {"classify": 7, "new_vertex": 51, "node_test": 32, "site_test": 25, "final_vertex": 60}
+PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (256 CUs x 2.4 GHz, packed FMA)
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--config", default="clustered_1m",
+                    help="uniform_10k | clustered_1m | power_uniform_1m | surface_20m | power_clustered_1m")
+    ap.add_argument("--n", type=int, default=None, help="override the site count")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--precision", type=int, default=1, help="1 fp32, 2 mixed fp32/fp64")
+    ap.add_argument("--leaf-size", type=int, default=0)
+    ap.add_argument("--culling", type=int, default=1)
+    ap.add_argument("--traversal", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    return ap.parse_args()
+
+
+def cpu_baseline(xyz, w, box, seconds: float) -> dict:
+    """The CPU oracle (FP64 brute-force clipper, all host threads) on a random
+    sample of cells of the same workload; scaled to cells per second."""
+    import numpy as np
+    import oracle
+    n = len(xyz)
+    rng = np.random.default_rng(12345)
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
+    m0 = min(n, max(threads, 32))
+    ids = np.sort(rng.choice(n, m0, replace=False))
+    t0 = time.perf_counter()
+    oracle.cells(xyz, w, box, ids=ids, threads=threads)
+    dt = time.perf_counter() - t0
+    rate = m0 / max(dt, 1e-9)
+    m = int(min(n, max(m0, rate * seconds)))
+    ids = np.sort(rng.choice(n, m, replace=False))
+    t0 = time.perf_counter()
+    oracle.cells(xyz, w, box, ids=ids, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": m / dt, "unit": "cells/s", "cores": threads, "kind": "oracle",
+            "sample": "%d random cells of the same %d-site workload, FP64 oracle with robustness margins, %.1f s"
+                      % (m, n, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import paper_2605_06408_amd as vd
+    from paper_2605_06408_amd import workloads as wl
+
+    xyz, w, box = wl.make(args.config, args.seed, args.n)
+    n = len(xyz)
+    dev = torch.device("cuda", 0)
+    tx = torch.from_numpy(xyz).to(dev)
+    tw = None if w is None else torch.from_numpy(w).to(dev)
+    bbox = [float(v) for v in box]
+    ctx = vd.Context(0)
+    kw = dict(precision=args.precision, leaf_size=args.leaf_size, culling=args.culling, traversal=args.traversal)
+
+    def step(profile=False, counters=False):
+        sz = ctx.build_sizes(tx, tw, bbox, profile=profile, counters=counters, **kw)
+        return ctx.write(sz)
+
+    # work counters from one untimed build (counting adds scalar work)
+    step(counters=True)
+    torch.cuda.synchronize()
+    ctr = ctx.counters()
+    for _ in range(args.warmup):
+        d = step(profile=True)
+    torch.cuda.synchronize()
+    clip_ms, phases = [], {k: 0.0 for k in vd.PHASES}
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        d = step(profile=True)
+        tm = ctx.timings()
+        clip_ms.append(tm["clip"])
+        for k in phases:
+            phases[k] += tm[k] / args.steps
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms = (t1 - t0) * 1000.0 / args.steps
+    sizes = d.sizes
+
+    flops = sum(ctr[k] * FLOPS_PER_UNIT[k] for k in FLOPS_PER_UNIT)
+    clip_s = float(np.mean(clip_ms)) / 1000.0
+    achieved = flops / clip_s / 1e12
+    roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "kernel": "k_clip<1,4> (64-vertex tier)", "kernel_ms": clip_s * 1000.0,
+                "flops_per_launch": flops}
+
+    out = {
+        "metric": METRIC, "value": n / (ms / 1000.0), "unit": "cells/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.config, "n": n, "seed": args.seed, "box": bbox,
+                   "weights": w is not None, "precision": "fp32" if args.precision == 1 else "mixed fp32/fp64",
+                   "leaf_size": args.leaf_size or 16, "culling": args.culling, "traversal": args.traversal},
+        "roofline": roofline,
+        "phases_ms": phases,
+        "counters": ctr,
+        "sizes": sizes,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(xyz, w, box, args.cpu_seconds)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

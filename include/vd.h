@@ -57,8 +57,31 @@ typedef struct vd_options {
     int32_t leaf_size;  /* sites per BVH leaf, 1..64 (default 16) */
     int32_t culling;    /* 1 = directional (Sec. 4.2.1, default), 2 = isotropic radius */
     int32_t traversal;  /* 1 = best-first (Alg. 1, default), 2 = depth-first */
-    int32_t reserved[4];
+    int32_t profile;    /* 1 = record per-phase HIP-event timings (vd_get_timings) */
+    int32_t counters;   /* 1 = count the method's work units (vd_get_counters) */
+    int32_t reserved[2];
 } vd_options;
+
+/* Phases reported by vd_get_timings (milliseconds, HIP events on `stream`). */
+#define VD_PHASE_LBVH 0       /* packing, Morton codes, radix sort, tree, bounds */
+#define VD_PHASE_CLIP 1       /* traversal + clipping, 64-vertex tier (one kernel) */
+#define VD_PHASE_CLIP_LARGE 2 /* traversal + clipping, 256- and 1024-vertex tiers */
+#define VD_PHASE_SCAN 3       /* prefix sums of the per-cell counts */
+#define VD_PHASE_BUILD 4      /* the whole vd_build, first to last device operation */
+#define VD_PHASE_WRITE 5      /* vd_write (CSR write-out and copies) */
+#define VD_PHASE_CLIP_TIER1 6 /* the 256-vertex tier alone (part of VD_PHASE_CLIP_LARGE) */
+#define VD_PHASE_COUNT 7
+
+/* Work units counted when vd_options.counters = 1 (whole build, all tiers). */
+#define VD_CTR_CLASSIFY 0     /* vertex-versus-plane side tests */
+#define VD_CTR_NEW_VERTEX 1   /* vertices created by clipping */
+#define VD_CTR_NODE_TEST 2    /* BVH child-box tests (Sec. 4.2.2) */
+#define VD_CTR_SITE_TEST 3    /* per-site plane-distance tests in leaves (Sec. 4.2.1) */
+#define VD_CTR_FINAL_VERTEX 4 /* vertices of the finished cells */
+#define VD_CTR_CLIP 5         /* clip attempts (candidate planes that passed the tests) */
+#define VD_CTR_CLIP_EFFECTIVE 6 /* clips that changed the cell */
+#define VD_CTR_LEAF 7         /* leaves visited */
+#define VD_CTR_COUNT 8
 
 /* Result sizes of the last vd_build. */
 typedef struct vd_sizes {
@@ -72,6 +95,7 @@ typedef struct vd_sizes {
     int64_t n_uncertain;/* cells flagged VD_FLAG_UNCERTAIN */
     int64_t n_failed;   /* cells flagged VD_FLAG_FAILED (status VD_ERR_CAPACITY) */
     int64_t n_fp64;     /* cells with at least one FP64 re-evaluation */
+    int64_t n_huge;     /* cells that needed the 1024-vertex pass */
 } vd_sizes;
 
 /* Output arrays: caller-owned device memory, sized from vd_sizes.  Rows are
@@ -139,6 +163,13 @@ VD_API vd_status vd_write(vd_context* ctx, const vd_outputs* out, void* stream);
 
 /* Counters of the last build (see vd_sizes); host call, no device work. */
 VD_API vd_status vd_get_sizes(const vd_context* ctx, vd_sizes* sizes);
+
+/* Per-phase times of the last build/write, ms[VD_PHASE_*]; needs
+ * vd_options.profile = 1 on that build.  Waits for the recorded events. */
+VD_API vd_status vd_get_timings(vd_context* ctx, float* ms, int32_t count);
+
+/* Work counters of the last build, out[VD_CTR_*]; needs vd_options.counters = 1. */
+VD_API vd_status vd_get_counters(const vd_context* ctx, uint64_t* out, int32_t count);
 
 /* Message for the last error on this thread ("" if none). */
 VD_API const char* vd_last_error(void);

@@ -89,7 +89,8 @@ def cells(xyz, w=None, box=None, ids=None, margin: bool = True, threads: int = 0
     if w is not None:
         w = np.ascontiguousarray(w, dtype=np.float32)
         assert w.shape == (n,)
-    box = default_box(xyz) if box is None else np.ascontiguousarray(box, dtype=np.float64)
+    # the clip box is an FP32 input like the sites: use its FP32 value exactly
+    box = default_box(xyz) if box is None else np.asarray(box, dtype=np.float32).astype(np.float64)
     if ids is not None:
         ids = np.ascontiguousarray(ids, dtype=np.int64)
         m = ids.shape[0]

@@ -34,6 +34,9 @@ TRAVERSAL_DEPTH_FIRST = 2
 
 MAX_SITES = 1 << 25
 
+PHASES = ("lbvh", "clip", "clip_large", "scan", "build", "write", "clip_tier1")
+COUNTERS = ("classify", "new_vertex", "node_test", "site_test", "final_vertex", "clip", "clip_effective", "leaf")
+
 STATUS = {0: "VD_OK", 1: "VD_ERR_INVALID_ARG", 2: "VD_ERR_HIP", 3: "VD_ERR_OOM", 4: "VD_ERR_STATE",
           5: "VD_ERR_CAPACITY"}
 
@@ -46,12 +49,13 @@ class VDError(RuntimeError):
 
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("culling", ctypes.c_int32),
-                ("traversal", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+                ("traversal", ctypes.c_int32), ("profile", ctypes.c_int32), ("counters", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 class Sizes(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("n", "n_nbr", "n_facet", "n_vert", "n_fv", "n_empty", "n_large",
-                                               "n_uncertain", "n_failed", "n_fp64")]
+                                               "n_uncertain", "n_failed", "n_fp64", "n_huge")]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -98,6 +102,10 @@ def load_library():
             lib.vd_last_error.argtypes = []
             lib.vd_version.restype = ctypes.c_char_p
             lib.vd_version.argtypes = []
+            lib.vd_get_timings.restype = ctypes.c_int
+            lib.vd_get_timings.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int32]
+            lib.vd_get_counters.restype = ctypes.c_int
+            lib.vd_get_counters.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32]
             _lib = lib
     return _lib
 
@@ -140,7 +148,8 @@ class Context:
             pass
 
     def build_sizes(self, xyz, w=None, bbox=None, precision=PRECISION_FP32, leaf_size=0,
-                    culling=CULLING_DIRECTIONAL, traversal=TRAVERSAL_BEST_FIRST, allow_failed=False) -> Sizes:
+                    culling=CULLING_DIRECTIONAL, traversal=TRAVERSAL_BEST_FIRST, allow_failed=False,
+                    profile=False, counters=False) -> Sizes:
         """Run vd_build only (the diagram stays in the context)."""
         import torch
         if not (xyz.is_cuda and xyz.dtype == torch.float32 and xyz.dim() == 2 and xyz.shape[1] == 3):
@@ -157,7 +166,7 @@ class Context:
             if len(vals) != 6:
                 raise ValueError("bbox must have 6 entries")
             hb = (ctypes.c_float * 6)(*vals)
-        opt = Options(precision, leaf_size, culling, traversal)
+        opt = Options(precision, leaf_size, culling, traversal, int(profile), int(counters))
         sz = Sizes()
         stream = torch.cuda.current_stream(self.device).cuda_stream
         with torch.cuda.device(self.device):
@@ -189,6 +198,18 @@ class Context:
         with torch.cuda.device(dev):
             _check(self.lib.vd_write(self.handle, ctypes.byref(out), ctypes.c_void_p(stream)), "vd_write")
         return Diagram(**t, sizes=sz.as_dict())
+
+    def timings(self) -> dict:
+        """Per-phase milliseconds of the last profiled build (and write)."""
+        ms = (ctypes.c_float * len(PHASES))()
+        _check(self.lib.vd_get_timings(self.handle, ms, len(PHASES)), "vd_get_timings")
+        return dict(zip(PHASES, [float(x) for x in ms]))
+
+    def counters(self) -> dict:
+        """Work counters of the last build made with counters=True."""
+        v = (ctypes.c_uint64 * len(COUNTERS))()
+        _check(self.lib.vd_get_counters(self.handle, v, len(COUNTERS)), "vd_get_counters")
+        return dict(zip(COUNTERS, [int(x) for x in v]))
 
     def build(self, xyz, w=None, bbox=None, **kw) -> Diagram:
         sz = self.build_sizes(xyz, w, bbox, **kw)

@@ -34,7 +34,7 @@ struct vd_context {
     int num_cu = 0;
     // grow-only device scratch
     DevBuf pts, spts, keys[2], vals[2], inv, mark, child, pint, pleaf, range, counters, nodes, hist, stmp, bbox,
-        bpart, misc, loc, cnt_v, cnt_f, cnt_n, vol, cen, flags, offv, offf, offn, scan_tmp, list1, list2, stats;
+        bpart, misc, loc, cnt_v, cnt_f, cnt_n, vol, cen, flags, offv, offf, offn, scan_tmp, list1, list2, stats, ctr;
     DevBuf st_vert[3], st_code[3], st_fsize[3], st_fv[3];
     // last build
     bool valid = false;
@@ -42,6 +42,11 @@ struct vd_context {
     vd_sizes sizes{};
     const uint32_t* order = nullptr;
     int tier_slots[3] = {0, 0, 0};
+    // profiling: events e[0..6] bracket the build phases, e[7..8] the write
+    hipEvent_t ev[9] = {};
+    bool ev_ready = false;
+    bool profiled = false, write_profiled = false;
+    bool counted = false;
 };
 
 namespace {
@@ -94,6 +99,13 @@ vd_status ensure_stage(vd_context* c, int tier, int64_t slots) {
     return VD_OK;
 }
 
+vd_status ensure_events(vd_context* c) {
+    if (c->ev_ready) return VD_OK;
+    for (hipEvent_t& e : c->ev) VD_HIP(hipEventCreate(&e));
+    c->ev_ready = true;
+    return VD_OK;
+}
+
 vd::Stage stage_of(vd_context* c, int tier) {
     vd::Stage s;
     s.cap = kTierCap[tier];
@@ -135,8 +147,11 @@ VD_API void vd_destroy(vd_context* c) {
     DevBuf* all[] = {&c->pts, &c->spts, &c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->inv, &c->mark,
                      &c->child, &c->pint, &c->pleaf, &c->range, &c->counters, &c->nodes, &c->hist, &c->stmp,
                      &c->bbox, &c->bpart, &c->misc, &c->loc, &c->cnt_v, &c->cnt_f, &c->cnt_n, &c->vol, &c->cen,
-                     &c->flags, &c->offv, &c->offf, &c->offn, &c->scan_tmp, &c->list1, &c->list2, &c->stats};
+                     &c->flags, &c->offv, &c->offf, &c->offn, &c->scan_tmp, &c->list1, &c->list2, &c->stats,
+                     &c->ctr};
     for (DevBuf* b : all) release(*b);
+    if (c->ev_ready)
+        for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     for (int t = 0; t < 3; ++t) {
         release(c->st_vert[t]);
         release(c->st_code[t]);
@@ -180,6 +195,11 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     VD_HIP(hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const size_t N = (size_t)n;
+    const bool prof = o.profile != 0;
+    c->profiled = false;
+    c->write_profiled = false;
+    c->counted = false;
+    if (prof) VD_TRY(ensure_events(c));
 
     VD_TRY(ensure(c->pts, N * sizeof(float4)));
     VD_TRY(ensure(c->spts, N * sizeof(float4)));
@@ -214,11 +234,14 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     VD_TRY(ensure(c->list1, N * sizeof(uint32_t)));
     VD_TRY(ensure(c->list2, N * sizeof(uint32_t)));
     VD_TRY(ensure(c->stats, vd::kStatCount * sizeof(unsigned long long)));
+    VD_TRY(ensure(c->ctr, vd::kCtrCount * sizeof(unsigned long long)));
     VD_TRY(ensure_stage(c, 0, n));
 
     // misc: [0] error bits, [1..3] work counters, [4] tier-1 list count, [5] tier-2 list count
     uint32_t* misc = as<uint32_t>(c->misc);
+    if (prof) VD_HIP(hipEventRecord(c->ev[0], s));
     VD_HIP(hipMemsetAsync(misc, 0, 16 * sizeof(uint32_t), s));
+    if (o.counters) VD_HIP(hipMemsetAsync(c->ctr.p, 0, vd::kCtrCount * sizeof(unsigned long long), s));
     VD_HIP(hipMemsetAsync(c->stats.p, 0, vd::kStatCount * sizeof(unsigned long long), s));
     float4* pts = as<float4>(c->pts);
     float* dbbox = as<float>(c->bbox);
@@ -271,6 +294,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     a.cen = as<float>(c->cen);
     a.flags = as<uint8_t>(c->flags);
     a.stats = as<unsigned long long>(c->stats);
+    a.ctr = o.counters ? as<unsigned long long>(c->ctr) : nullptr;
 
     // tier 0: every cell
     a.tier = 0;
@@ -281,13 +305,16 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     a.next_count = misc + 4;
     a.stage = stage_of(c, 0);
     c->tier_slots[0] = (int)n;
+    if (prof) VD_HIP(hipEventRecord(c->ev[1], s));
     VD_HIP(vd::launch_clip(a, vd::clip_grid_waves(0, c->num_cu), s));
+    if (prof) VD_HIP(hipEventRecord(c->ev[2], s));
     uint32_t hmisc[16];
     VD_HIP(hipMemcpyAsync(hmisc, misc, sizeof(hmisc), hipMemcpyDeviceToHost, s));
     VD_HIP(hipStreamSynchronize(s));
     if (hmisc[0] & 1u) return fail(VD_ERR_INVALID_ARG, "vd_build: non-finite site coordinate or weight");
     if (hmisc[0] & 2u) return fail(VD_ERR_INVALID_ARG, "vd_build: degenerate bounding box");
     // larger tiers for the cells that outgrew the previous one
+    c->tier_slots[1] = c->tier_slots[2] = 0;
     for (int tier = 1; tier < 3; ++tier) {
         const uint32_t cnt = hmisc[3 + tier];
         c->tier_slots[tier] = (int)cnt;
@@ -303,8 +330,13 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
         int waves = vd::clip_grid_waves(tier, c->num_cu);
         if ((int64_t)waves > (int64_t)cnt) waves = (int)cnt;
         VD_HIP(vd::launch_clip(a, waves, s));
+        if (prof && tier == 1) VD_HIP(hipEventRecord(c->ev[6], s));
         VD_HIP(hipMemcpyAsync(hmisc, misc, sizeof(hmisc), hipMemcpyDeviceToHost, s));
         VD_HIP(hipStreamSynchronize(s));
+    }
+    if (prof) {
+        VD_HIP(hipEventRecord(c->ev[3], s));
+        if (c->tier_slots[1] == 0) VD_HIP(hipEventRecord(c->ev[6], s));
     }
     VD_HIP(vd::scan_counts(as<uint32_t>(c->cnt_v), n, as<int64_t>(c->offv), as<int64_t>(c->scan_tmp), s));
     VD_HIP(vd::scan_counts(as<uint32_t>(c->cnt_f), n, as<int64_t>(c->offf), as<int64_t>(c->scan_tmp), s));
@@ -314,8 +346,12 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     VD_HIP(hipMemcpyAsync(&tot[0], as<int64_t>(c->offv) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     VD_HIP(hipMemcpyAsync(&tot[1], as<int64_t>(c->offf) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     VD_HIP(hipMemcpyAsync(&tot[2], as<int64_t>(c->offn) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    if (prof) VD_HIP(hipEventRecord(c->ev[4], s));
     VD_HIP(hipMemcpyAsync(st, c->stats.p, sizeof(st), hipMemcpyDeviceToHost, s));
+    if (prof) VD_HIP(hipEventRecord(c->ev[5], s));
     VD_HIP(hipStreamSynchronize(s));
+    c->profiled = prof;
+    c->counted = o.counters != 0;
 
     vd_sizes z{};
     z.n = n;
@@ -328,6 +364,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     z.n_uncertain = (int64_t)st[vd::kStatUncertain];
     z.n_failed = (int64_t)st[vd::kStatFailed];
     z.n_fp64 = (int64_t)st[vd::kStatFP64];
+    z.n_huge = c->tier_slots[2];
     c->sizes = z;
     c->n = n;
     c->order = order;
@@ -346,6 +383,8 @@ VD_API vd_status vd_write(vd_context* c, const vd_outputs* out, void* stream) {
     VD_HIP(hipSetDevice(c->device));
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t n = c->n;
+    const bool prof = c->profiled;
+    if (prof) VD_HIP(hipEventRecord(c->ev[7], s));
     vd::WriteArgs a{};
     a.n = n;
     a.inv = as<uint32_t>(c->inv);
@@ -373,6 +412,39 @@ VD_API vd_status vd_write(vd_context* c, const vd_outputs* out, void* stream) {
     if (out->centroid)
         VD_HIP(hipMemcpyAsync(out->centroid, c->cen.p, 3 * (size_t)n * sizeof(float), hipMemcpyDeviceToDevice, s));
     if (out->flags) VD_HIP(hipMemcpyAsync(out->flags, c->flags.p, (size_t)n, hipMemcpyDeviceToDevice, s));
+    if (prof) {
+        VD_HIP(hipEventRecord(c->ev[8], s));
+        c->write_profiled = true;
+    }
+    return VD_OK;
+}
+
+VD_API vd_status vd_get_timings(vd_context* c, float* ms, int32_t count) {
+    if (!c || !ms || count < 0) return fail(VD_ERR_INVALID_ARG, "vd_get_timings: bad argument");
+    if (!c->valid || !c->profiled) return fail(VD_ERR_STATE, "vd_get_timings: last build was not profiled");
+    VD_HIP(hipSetDevice(c->device));
+    float t[VD_PHASE_COUNT] = {0, 0, 0, 0, 0, 0, 0};
+    VD_HIP(hipEventSynchronize(c->ev[5]));
+    VD_HIP(hipEventElapsedTime(&t[VD_PHASE_LBVH], c->ev[0], c->ev[1]));
+    VD_HIP(hipEventElapsedTime(&t[VD_PHASE_CLIP], c->ev[1], c->ev[2]));
+    VD_HIP(hipEventElapsedTime(&t[VD_PHASE_CLIP_LARGE], c->ev[2], c->ev[3]));
+    VD_HIP(hipEventElapsedTime(&t[VD_PHASE_SCAN], c->ev[3], c->ev[4]));
+    VD_HIP(hipEventElapsedTime(&t[VD_PHASE_BUILD], c->ev[0], c->ev[5]));
+    if (c->tier_slots[1] > 0) VD_HIP(hipEventElapsedTime(&t[VD_PHASE_CLIP_TIER1], c->ev[2], c->ev[6]));
+    if (c->write_profiled) {
+        VD_HIP(hipEventSynchronize(c->ev[8]));
+        VD_HIP(hipEventElapsedTime(&t[VD_PHASE_WRITE], c->ev[7], c->ev[8]));
+    }
+    for (int k = 0; k < count && k < VD_PHASE_COUNT; ++k) ms[k] = t[k];
+    return VD_OK;
+}
+
+VD_API vd_status vd_get_counters(const vd_context* c, uint64_t* out, int32_t count) {
+    if (!c || !out || count < 0) return fail(VD_ERR_INVALID_ARG, "vd_get_counters: bad argument");
+    if (!c->valid || !c->counted) return fail(VD_ERR_STATE, "vd_get_counters: last build did not count");
+    unsigned long long h[vd::kCtrCount];
+    VD_HIP(hipMemcpy(h, c->ctr.p, sizeof(h), hipMemcpyDeviceToHost));
+    for (int k = 0; k < count && k < vd::kCtrCount; ++k) out[k] = (uint64_t)h[k];
     return VD_OK;
 }
 

@@ -36,7 +36,7 @@ namespace {
 constexpr float kU = 5.9604645e-08f;  // FP32 unit roundoff 2^-24
 constexpr double kU64 = 1.1102230246251565e-16;
 
-enum ClipResult { kNone = 0, kChanged = 1, kEmptied = 2, kOverflow = 3 };
+enum ClipResult { kNone = 0, kChanged = 1, kEmptied = 2, kOverflow = 3, kRestart = 4 };
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 __device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
@@ -63,6 +63,10 @@ __device__ __forceinline__ float wsum(float v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return uni(v);
 }
+__device__ __forceinline__ double wsum64(double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
 __device__ __forceinline__ uint32_t wsum_u(uint32_t v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
@@ -85,6 +89,7 @@ struct WaveMem {
     static constexpr int CAP = 64 * VPL;
     float4 pl[CAP];        // planes: a.xyz, b (frame of the site)
     float psb[CAP];        // size of the terms b is formed from (error scale)
+    float4 psite[CAP];     // the plane's site (x, y, z, w) for exact re-evaluation
     int32_t pcode[CAP];    // Morton index of the plane's site, or box code -1..-6
     uint32_t ta[CAP];      // clip: new vertex by first old plane | finalize: plane rank
     uint32_t tb[CAP];      // clip: new vertex by second old plane | finalize: facet size
@@ -92,7 +97,7 @@ struct WaveMem {
     uint32_t sor[CAP];     // clip: free slot of rank | finalize: vertex renumbering
     uint32_t vtri[CAP];    // finalize: planes of each vertex
     uint32_t vadj[CAP];    // finalize: neighbours of each vertex
-    float4 vpos[CAP];      // finalize: positions
+    double vpx[CAP], vpy[CAP], vpz[CAP];  // finalize: FP64 positions relative to vertex 0
     int32_t key[CAP];      // finalize and gc: output codes, used flags
     uint8_t outf[CAP];     // outside flags by vertex index (VPL > 1)
 };
@@ -113,6 +118,7 @@ struct Cell {
     float px, py, pz, pw;
     uint32_t self;
     uint32_t flags;
+    int robust;   // 0: FP32 signs; 1: doubtful signs in FP64; 2: every sign in FP64
     // vertices: slot s of this lane is vertex s*64 + lane
     float y0[VPL], y1[VPL], y2[VPL], ev[VPL];
     uint32_t vt[VPL], va[VPL];
@@ -124,8 +130,18 @@ struct Cell {
     uint32_t qe[VPL];
     float qk[VPL];
     int qn;
+    // work counters (uniform), accumulated over all cells of this wave
+    uint64_t ctr[kCtrCount];
+    bool counting;
 
-    __device__ Cell(WaveMem<VPL>& m, const ClipArgs& a) : M(m), A(a), ln(lane_id()), serial(1) {}
+    __device__ Cell(WaveMem<VPL>& m, const ClipArgs& a) : M(m), A(a), ln(lane_id()), serial(1) {
+        counting = a.ctr != nullptr;
+#pragma unroll
+        for (int c = 0; c < kCtrCount; ++c) ctr[c] = 0;
+    }
+    __device__ __forceinline__ void count(int c, uint64_t v) {
+        if (counting) ctr[c] += v;
+    }
 
     // ------------------------------------------------------------ setup
     __device__ bool init(uint32_t k) {
@@ -196,8 +212,13 @@ struct Cell {
     }
 
     // ------------------------------------------------------------ FP64 side test
-    __device__ P64 plane64(int32_t code, double qx, double qy, double qz, double qw) const {
+    // Plane q (LDS) in FP64, recomputed from the input coordinates: a = p_j - p_i
+    // is exact in FP64, b = (|a|^2 + w_i - w_j) / 2 nearly so.
+    __device__ P64 plane64(uint32_t q) const { return plane64(M.pcode[q], M.psite[q]); }
+
+    __device__ P64 plane64(int32_t code, float4 site) const {
         P64 r;
+        const double qx = px, qy = py, qz = pz, qw = pw;
         if (code < 0) {
             int c = -code - 1, ax = c >> 1, side = c & 1;
             double p[3] = {qx, qy, qz};
@@ -206,44 +227,52 @@ struct Cell {
             if (ax == 0) r.a0 = sgn; else if (ax == 1) r.a1 = sgn; else r.a2 = sgn;
             r.b = side ? ((double)A.bbox[3 + ax] - p[ax]) : (p[ax] - (double)A.bbox[ax]);
         } else {
-            float4 q = A.pts[code];
-            r.a0 = (double)q.x - qx; r.a1 = (double)q.y - qy; r.a2 = (double)q.z - qz;
-            r.b = 0.5 * (r.a0 * r.a0 + r.a1 * r.a1 + r.a2 * r.a2 + (qw - (double)q.w));
+            r.a0 = (double)site.x - qx; r.a1 = (double)site.y - qy; r.a2 = (double)site.z - qz;
+            r.b = 0.5 * (r.a0 * r.a0 + r.a1 * r.a1 + r.a2 * r.a2 + (qw - (double)site.w));
         }
         return r;
     }
 
-    // Side of vertex (planes t) w.r.t. plane h, recomputed in FP64 from the
-    // input coordinates.  Returns +1 outside, -1 inside, 0 undecided.
-    __device__ int side64(uint32_t t, const P64& h) const {
-        double qx = px, qy = py, qz = pz, qw = pw;
-        P64 A0 = plane64(M.pcode[f10(t, 0)], qx, qy, qz, qw);
-        P64 B0 = plane64(M.pcode[f10(t, 1)], qx, qy, qz, qw);
-        P64 C0 = plane64(M.pcode[f10(t, 2)], qx, qy, qz, qw);
+    // Intersection of three FP64 planes: numerator n and determinant (y = n / det).
+    __device__ static void cramer64(const P64& A0, const P64& B0, const P64& C0, double* n, double* det) {
         double bc0 = B0.a1 * C0.a2 - B0.a2 * C0.a1, bc1 = B0.a2 * C0.a0 - B0.a0 * C0.a2,
                bc2 = B0.a0 * C0.a1 - B0.a1 * C0.a0;
         double ca0 = C0.a1 * A0.a2 - C0.a2 * A0.a1, ca1 = C0.a2 * A0.a0 - C0.a0 * A0.a2,
                ca2 = C0.a0 * A0.a1 - C0.a1 * A0.a0;
         double ab0 = A0.a1 * B0.a2 - A0.a2 * B0.a1, ab1 = A0.a2 * B0.a0 - A0.a0 * B0.a2,
                ab2 = A0.a0 * B0.a1 - A0.a1 * B0.a0;
-        double det = A0.a0 * bc0 + A0.a1 * bc1 + A0.a2 * bc2;
-        double n0 = A0.b * bc0 + B0.b * ca0 + C0.b * ab0;
-        double n1 = A0.b * bc1 + B0.b * ca1 + C0.b * ab1;
-        double n2 = A0.b * bc2 + B0.b * ca2 + C0.b * ab2;
+        *det = A0.a0 * bc0 + A0.a1 * bc1 + A0.a2 * bc2;
+        n[0] = A0.b * bc0 + B0.b * ca0 + C0.b * ab0;
+        n[1] = A0.b * bc1 + B0.b * ca1 + C0.b * ab1;
+        n[2] = A0.b * bc2 + B0.b * ca2 + C0.b * ab2;
+    }
+
+    // Side of vertex (planes t) w.r.t. plane h, recomputed in FP64 from the
+    // input coordinates.  Returns +1 outside, -1 inside, 0 undecided.
+    __device__ int side64(uint32_t t, const P64& h) const {
+        double n[3], det;
+        cramer64(plane64(f10(t, 0)), plane64(f10(t, 1)), plane64(f10(t, 2)), n, &det);
         // s * det = a_h . n - b_h det, evaluated without dividing
-        double s = h.a0 * n0 + h.a1 * n1 + h.a2 * n2 - h.b * det;
+        double s = h.a0 * n[0] + h.a1 * n[1] + h.a2 * n[2] - h.b * det;
         if (det < 0) s = -s;
-        double scale = (fabs(h.a0) + fabs(h.a1) + fabs(h.a2)) * (fabs(n0) + fabs(n1) + fabs(n2)) + fabs(h.b * det);
+        double scale = (fabs(h.a0) + fabs(h.a1) + fabs(h.a2)) * (fabs(n[0]) + fabs(n[1]) + fabs(n[2])) +
+                       fabs(h.b * det);
         if (fabs(s) <= 64.0 * kU64 * scale) return 0;
         return s > 0 ? 1 : -1;
     }
 
     // ------------------------------------------------------------ clip
     // mode 0: plain FP32 signs; 1: doubtful signs re-evaluated in FP64;
-    // 2: doubtful signs taken as inside (fallback after an inconsistency).
-    __device__ void classify(float ax, float ay, float az, float b, float sbh, int32_t hcode, int mode,
-                             uint64_t* R) {
+    // 2: doubtful signs taken as inside; 3: every sign evaluated in FP64.
+    __device__ void classify(float ax, float ay, float az, float b, float sbh, int32_t hcode, float4 hsite,
+                             int mode, uint64_t* R) {
         const float an1 = fabsf(ax) + fabsf(ay) + fabsf(az);
+        if (counting && mode != 2) {
+            uint64_t nal = 0;
+#pragma unroll
+            for (int s = 0; s < VPL; ++s) nal += (uint64_t)popc(alive[s]);
+            count(kCtrClassify, nal);
+        }
         uint64_t amb_any = 0;
         bool amb[VPL];
 #pragma unroll
@@ -253,16 +282,16 @@ struct Cell {
             bool o = al && sv > 0.f;
             amb[s] = false;
             if (mode != 0) {
-                float beta = 32.f * kU * (an1 * ev[s] + sbh);
-                amb[s] = al && fabsf(sv) <= beta;
+                float beta = 64.f * kU * (an1 * ev[s] + sbh);
+                amb[s] = al && (mode == 3 || fabsf(sv) <= beta);
                 if (amb[s] && mode == 2) o = false;
             }
             R[s] = ballot(o);
             amb_any |= ballot(amb[s]);
         }
-        if (mode == 1 && amb_any) {
+        if ((mode == 1 || mode == 3) && amb_any) {
             flags |= kFlagFP64;
-            P64 h = plane64(hcode, (double)px, (double)py, (double)pz, (double)pw);
+            P64 h = plane64(hcode, hsite);
 #pragma unroll
             for (int s = 0; s < VPL; ++s) {
                 bool o = (R[s] >> ln) & 1;
@@ -281,7 +310,7 @@ struct Cell {
     // Tries the clip with the given outside masks; on an inconsistent
     // boundary returns false and leaves the cell untouched.
     __device__ int apply(const uint64_t* R, float ax, float ay, float az, float b, float sbh, int32_t hcode,
-                         bool* consistent) {
+                         float4 hsite, bool* consistent) {
         *consistent = true;
         bool any = false, all = true;
 #pragma unroll
@@ -386,6 +415,22 @@ struct Cell {
                 nb2[s] = a2 & 4095u;
             }
         }
+        if (!ballot(bad)) {
+            // the new vertices must form one cycle around the new facet:
+            // following "next around h" from the first one returns after m steps
+            const uint32_t start = (uint32_t)__builtin_amdgcn_readfirstlane((int)M.sor[0]);
+            uint32_t v = start, steps = 0;
+            do {
+                const uint32_t sl = v >> 6, lv = v & 63;
+                uint32_t nxt = 0xFFFFFFFFu;
+#pragma unroll
+                for (int s = 0; s < VPL; ++s)
+                    if ((uint32_t)s == sl) nxt = rdl(nb1[s], (int)lv);
+                v = nxt;
+                ++steps;
+            } while (v != start && steps <= m);
+            bad = steps != m;
+        }
         if (ballot(bad)) {
             *consistent = false;
             return kNone;
@@ -429,23 +474,30 @@ struct Cell {
             M.pl[h] = make_float4(ax, ay, az, b);
             M.psb[h] = sbh;
             M.pcode[h] = hcode;
+            M.psite[h] = hsite;
         }
         np = (int)h + 1;
         wave_sync();
+        count(kCtrNewVertex, m);
+        count(kCtrEffective, 1);
         return kChanged;
     }
 
-    __device__ int clip(float ax, float ay, float az, float b, float sbh, int32_t hcode) {
+    // Plain FP32 signs unless the cell is being rebuilt robustly; an
+    // inconsistent boundary in FP32 asks for that rebuild, in the robust mode
+    // doubtful signs fall back to "inside" and, failing that, the plane is
+    // skipped and the cell flagged.
+    __device__ int clip(float ax, float ay, float az, float b, float sbh, int32_t hcode, float4 hsite) {
         uint64_t R[VPL];
-        const int mode = A.precision == 2 ? 1 : 0;
-        classify(ax, ay, az, b, sbh, hcode, mode, R);
+        count(kCtrClip, 1);
+        classify(ax, ay, az, b, sbh, hcode, hsite, robust == 0 ? 0 : (robust == 1 ? 1 : 3), R);
         bool ok;
-        int r = apply(R, ax, ay, az, b, sbh, hcode, &ok);
+        int r = apply(R, ax, ay, az, b, sbh, hcode, hsite, &ok);
         if (ok) return r;
-        // inconsistent boundary: take doubtful signs as inside and retry once
+        if (robust < 2) return kRestart;
         flags |= kFlagUncertain;
-        classify(ax, ay, az, b, sbh, hcode, 2, R);
-        r = apply(R, ax, ay, az, b, sbh, hcode, &ok);
+        classify(ax, ay, az, b, sbh, hcode, hsite, 2, R);
+        r = apply(R, ax, ay, az, b, sbh, hcode, hsite, &ok);
         return ok ? r : kNone;
     }
 
@@ -461,7 +513,7 @@ struct Cell {
                 M.key[f10(vt[s], 2)] = 1;
             }
         wave_sync();
-        float4 pl[VPL];
+        float4 pl[VPL], ps[VPL];
         float sb[VPL];
         int32_t pc[VPL];
         uint32_t dst[VPL];
@@ -476,6 +528,7 @@ struct Cell {
             cnt += popc(u);
             if (used[s]) {
                 pl[s] = M.pl[q];
+                ps[s] = M.psite[q];
                 sb[s] = M.psb[q];
                 pc[s] = M.pcode[q];
             }
@@ -486,6 +539,7 @@ struct Cell {
             int q = s * 64 + ln;
             if (used[s]) {
                 M.pl[dst[s]] = pl[s];
+                M.psite[dst[s]] = ps[s];
                 M.psb[dst[s]] = sb[s];
                 M.pcode[dst[s]] = pc[s];
                 M.key[q] = (int32_t)dst[s];
@@ -602,11 +656,14 @@ struct Cell {
     // Clips by the candidate sites of one leaf; nearest plane first.
     __device__ int leaf(uint32_t ref) {
         const uint32_t first = leaf_first(ref), count = leaf_count(ref);
+        this->count(kCtrLeaf, 1);
+        this->count(kCtrSite, count);
         float ax = 0.f, ay = 0.f, az = 0.f, a2 = 0.f, b = 0.f, dw = 0.f, key = INFINITY;
+        float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
         bool cand = false;
         if (ln < count) {
             uint32_t j = first + ln;
-            float4 q = A.pts[j];
+            q = A.pts[j];
             if (j != self && q.w != -INFINITY) {
                 ax = q.x - px; ay = q.y - py; az = q.z - pz;
                 a2 = fmaf(ax, ax, fmaf(ay, ay, az * az));
@@ -636,8 +693,9 @@ struct Cell {
             mask &= ~(1ull << L);
             float hx = rdl(ax, L), hy = rdl(ay, L), hz = rdl(az, L), hb = rdl(b, L);
             float sb = 0.5f * (rdl(a2, L) + fabsf(rdl(dw, L)));
-            int r = clip(hx, hy, hz, hb, sb, (int32_t)(first + (uint32_t)L));
-            if (r == kEmptied || r == kOverflow) return r;
+            float4 hs = make_float4(rdl(q.x, L), rdl(q.y, L), rdl(q.z, L), rdl(q.w, L));
+            int r = clip(hx, hy, hz, hb, sb, (int32_t)(first + (uint32_t)L), hs);
+            if (r == kEmptied || r == kOverflow || r == kRestart) return r;
             if (r == kChanged) {
                 update_bounds();
                 mask &= ballot(keep(true));
@@ -663,6 +721,7 @@ struct Cell {
         for (;;) {
             while (have && !ref_is_leaf(cur)) {
                 if (--budget < 0) return kOverflow;
+                count(kCtrNode, 2);
                 const uint32_t node = cur;
                 float key = 0.f, delta = 0.f;
                 bool cull = true;
@@ -699,6 +758,7 @@ struct Cell {
                 uint32_t e;
                 float k;
                 pop(&e, &k);
+                count(kCtrNode, 1);
                 if (A.traversal != 2 && k > sqrtf(rmax2) * (1.f + 16.f * kU)) {
                     qn = 0;  // every key left is at least k: nothing can cut the cell
                     break;
@@ -723,7 +783,21 @@ struct Cell {
     }
 
     // ------------------------------------------------------------ output
-    __device__ void finalize(uint32_t slot, uint32_t orig) {
+    // FP64 position of a vertex (relative to the site) from its three planes.
+    __device__ void pos64(uint32_t t, float fx, float fy, float fz, double* y) const {
+        double n[3], det;
+        cramer64(plane64(f10(t, 0)), plane64(f10(t, 1)), plane64(f10(t, 2)), n, &det);
+        if (det != 0.0) {
+            double inv = 1.0 / det;
+            y[0] = n[0] * inv; y[1] = n[1] * inv; y[2] = n[2] * inv;
+        } else {
+            y[0] = fx; y[1] = fy; y[2] = fz;
+        }
+    }
+
+    // Writes the cell's record.  Returns false if the vertex/facet structure
+    // is not a closed simple polytope (the caller then rebuilds the cell).
+    __device__ bool finalize(uint32_t slot, uint32_t orig) {
         gc();
         const int F = np;
         // facet order: ascending output code (box faces -6..-1, then original site ids)
@@ -740,117 +814,139 @@ struct Cell {
             M.tb[q] = 0;
             M.edge[q] = 0xFFFFFFFFu;
         }
-        wave_sync();
         const Stage& st = A.stage;
         int32_t* codes = st.code + (int64_t)slot * st.cap;
         for (int q = ln; q < F; q += 64) codes[M.ta[q]] = M.key[q];
-        // vertex renumbering 0..nv-1
+        // vertex renumbering 0..nv-1 (slot-major)
         uint32_t vid[VPL];
         uint32_t nv = 0;
+        int s0 = -1;
 #pragma unroll
         for (int s = 0; s < VPL; ++s) {
             vid[s] = nv + mbcnt(alive[s]);
+            if (s0 < 0 && alive[s]) s0 = s;
             nv += popc(alive[s]);
             if ((alive[s] >> ln) & 1) M.sor[s * 64 + ln] = vid[s];
         }
         wave_sync();
+        if (s0 < 0) return false;
+        // reference point of the tetrahedral fan: vertex 0, in FP64
+        double ref[3] = {0.0, 0.0, 0.0};
+        {
+            const int l0 = lowest(alive[s0]);
+            double y[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+            for (int s = 0; s < VPL; ++s)
+                if (s == s0 && (int)ln == l0) pos64(vt[s], y0[s], y1[s], y2[s], y);
+            for (int c = 0; c < 3; ++c) ref[c] = __shfl(y[c], l0);
+        }
+        float4* vout = st.vert + (int64_t)slot * st.cap;
+        const double p64[3] = {(double)px, (double)py, (double)pz};
 #pragma unroll
         for (int s = 0; s < VPL; ++s) {
             if ((alive[s] >> ln) & 1) {
                 uint32_t t0 = M.ta[f10(vt[s], 0)], t1 = M.ta[f10(vt[s], 1)], t2 = M.ta[f10(vt[s], 2)];
                 uint32_t a0 = M.sor[f10(va[s], 0)], a1 = M.sor[f10(va[s], 1)], a2 = M.sor[f10(va[s], 2)];
-                M.vtri[vid[s]] = t0 | (t1 << 10) | (t2 << 20);
-                M.vadj[vid[s]] = a0 | (a1 << 10) | (a2 << 20);
-                M.vpos[vid[s]] = make_float4(y0[s], y1[s], y2[s], 0.f);
+                const uint32_t v = vid[s];
+                M.vtri[v] = t0 | (t1 << 10) | (t2 << 20);
+                M.vadj[v] = a0 | (a1 << 10) | (a2 << 20);
+                double y[3];
+                pos64(vt[s], y0[s], y1[s], y2[s], y);
+                M.vpx[v] = y[0] - ref[0];
+                M.vpy[v] = y[1] - ref[1];
+                M.vpz[v] = y[2] - ref[2];
+                uint32_t u0 = t0, u1 = t1, u2 = t2, tmp;
+                if (u0 > u1) { tmp = u0; u0 = u1; u1 = tmp; }
+                if (u1 > u2) { tmp = u1; u1 = u2; u2 = tmp; }
+                if (u0 > u1) { tmp = u0; u0 = u1; u1 = tmp; }
+                vout[v] = make_float4((float)(p64[0] + y[0]), (float)(p64[1] + y[1]), (float)(p64[2] + y[2]),
+                                      __uint_as_float(u0 | (u1 << 10) | (u2 << 20)));
                 atomicAdd(&M.tb[t0], 1u);
                 atomicAdd(&M.tb[t1], 1u);
                 atomicAdd(&M.tb[t2], 1u);
-                atomicMin(&M.edge[t0], vid[s]);
-                atomicMin(&M.edge[t1], vid[s]);
-                atomicMin(&M.edge[t2], vid[s]);
+                atomicMin(&M.edge[t0], v);
+                atomicMin(&M.edge[t1], v);
+                atomicMin(&M.edge[t2], v);
             }
         }
         wave_sync();
-        // facet sizes, offsets and vertex rings (CCW seen from outside)
+        // facet rings in output (rank) order, counter-clockwise seen from outside;
+        // sizes and anchors (lowest vertex) are indexed by facet rank
         uint16_t* fs = st.fsize + (int64_t)slot * st.cap;
         uint16_t* fvp = st.fv + (int64_t)slot * 3 * st.cap;
         uint32_t carry = 0;
         bool bad = false;
-        for (int q0 = 0; q0 < F; q0 += 64) {
-            int q = q0 + (int)ln;
-            uint32_t sz = q < F ? M.tb[q] : 0u;
+        for (int r0 = 0; r0 < F; r0 += 64) {
+            const uint32_t r = (uint32_t)(r0 + (int)ln);
+            uint32_t sz = r < (uint32_t)F ? M.tb[r] : 0u;
             uint32_t x = sz;
             for (int o = 1; o < 64; o <<= 1) {
                 uint32_t y = __shfl_up(x, o);
                 if ((int)ln >= o) x += y;
             }
-            if (q < F) {
-                fs[q] = (uint16_t)sz;
-                uint32_t base = carry + x - sz;
-                uint32_t start = M.edge[q], v = start, t = 0;
-                do {
-                    fvp[base + t] = (uint16_t)v;
-                    ++t;
-                    uint32_t tri = M.vtri[v], adj = M.vadj[v];
-                    int k = f10(tri, 0) == (uint32_t)q ? 0 : (f10(tri, 1) == (uint32_t)q ? 1 : 2);
-                    v = f10(adj, (k + 1) % 3);
-                } while (v != start && t < sz);
-                bad |= (v != start) || (t != sz);
+            if (r < (uint32_t)F) {
+                fs[r] = (uint16_t)sz;
+                const uint32_t base = carry + x - sz, start = M.edge[r];
+                if (sz < 3 || start >= nv) {
+                    bad = true;
+                } else {
+                    uint32_t v = start, t = 0;
+                    do {
+                        fvp[base + t] = (uint16_t)v;
+                        ++t;
+                        uint32_t tri = M.vtri[v], adj = M.vadj[v];
+                        uint32_t k = f10(tri, 0) == r ? 0u : (f10(tri, 1) == r ? 1u : 2u);
+                        v = f10(adj, (k + 1) % 3);
+                    } while (v != start && t < sz && v < nv);
+                    bad |= (v != start) || (t != sz);
+                }
             }
             carry += (uint32_t)__shfl(x, 63);
         }
-        if (ballot(bad)) flags |= kFlagUncertain;
-        // positions (global) and sorted facet triples; volume and centroid
-        // from the tetrahedra (ref, anchor_f, v, next_f(v))
-        const float4 ref = M.vpos[0];
-        float4* vout = st.vert + (int64_t)slot * st.cap;
-        float vol6 = 0.f, mx = 0.f, my = 0.f, mz = 0.f;
+        if (ballot(bad)) return false;
+        // volume and centroid from the tetrahedra (ref, anchor_f, v, next_f(v)),
+        // accumulated in FP64 (thin cells cancel badly in FP32)
+        double vol6 = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
         for (uint32_t v = ln; v < nv; v += 64) {
-            float4 P = M.vpos[v];
+            const double Px = M.vpx[v], Py = M.vpy[v], Pz = M.vpz[v];
             uint32_t tri = M.vtri[v], adj = M.vadj[v];
-            uint32_t t0 = f10(tri, 0), t1 = f10(tri, 1), t2 = f10(tri, 2), tmp;
-            if (t0 > t1) { tmp = t0; t0 = t1; t1 = tmp; }
-            if (t1 > t2) { tmp = t1; t1 = t2; t2 = tmp; }
-            if (t0 > t1) { tmp = t0; t0 = t1; t1 = tmp; }
-            vout[v] = make_float4(px + P.x, py + P.y, pz + P.z, __uint_as_float(t0 | (t1 << 10) | (t2 << 20)));
-            float bx = P.x - ref.x, by = P.y - ref.y, bz = P.z - ref.z;
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                uint32_t f = f10(tri, k);
-                uint32_t an = M.edge[f];
+                uint32_t an = M.edge[f10(tri, k)];
                 uint32_t nx = f10(adj, (k + 1) % 3);
                 if (an == v || nx == an) continue;
-                float4 Q = M.vpos[an], N = M.vpos[nx];
-                float qx = Q.x - ref.x, qy = Q.y - ref.y, qz = Q.z - ref.z;
-                float nxx = N.x - ref.x, nyy = N.y - ref.y, nzz = N.z - ref.z;
-                // det(anchor, v, next) relative to ref
-                float cx = by * nzz - bz * nyy, cy = bz * nxx - bx * nzz, cz = bx * nyy - by * nxx;
-                float det = fmaf(qx, cx, fmaf(qy, cy, qz * cz));
+                const double Qx = M.vpx[an], Qy = M.vpy[an], Qz = M.vpz[an];
+                const double Nx = M.vpx[nx], Ny = M.vpy[nx], Nz = M.vpz[nx];
+                // det(anchor, v, next) relative to the reference vertex
+                double cx = Py * Nz - Pz * Ny, cy = Pz * Nx - Px * Nz, cz = Px * Ny - Py * Nx;
+                double det = Qx * cx + Qy * cy + Qz * cz;
                 vol6 += det;
-                mx += det * (qx + bx + nxx);
-                my += det * (qy + by + nyy);
-                mz += det * (qz + bz + nzz);
+                mx += det * (Qx + Px + Nx);
+                my += det * (Qy + Py + Ny);
+                mz += det * (Qz + Pz + Nz);
             }
         }
-        vol6 = wsum(vol6);
-        mx = wsum(mx);
-        my = wsum(my);
-        mz = wsum(mz);
+        vol6 = wsum64(vol6);
+        mx = wsum64(mx);
+        my = wsum64(my);
+        mz = wsum64(mz);
         uint32_t nbox = 0;
         for (int q = ln; q < F; q += 64) nbox += M.key[q] < 0 ? 1u : 0u;
         nbox = wsum_u(nbox);
+        count(kCtrFinal, nv);
         if (ln == 0) {
             A.cnt_v[orig] = nv;
             A.cnt_f[orig] = (uint32_t)F;
             A.cnt_n[orig] = (uint32_t)F - nbox;
-            A.vol[orig] = vol6 / 6.f;
-            float inv = vol6 != 0.f ? 0.25f / vol6 : 0.f;
-            A.cen[3 * orig] = px + ref.x + mx * inv;
-            A.cen[3 * orig + 1] = py + ref.y + my * inv;
-            A.cen[3 * orig + 2] = pz + ref.z + mz * inv;
+            A.vol[orig] = (float)(vol6 / 6.0);
+            double inv = vol6 != 0.0 ? 0.25 / vol6 : 0.0;
+            A.cen[3 * orig] = (float)(p64[0] + ref[0] + mx * inv);
+            A.cen[3 * orig + 1] = (float)(p64[1] + ref[1] + my * inv);
+            A.cen[3 * orig + 2] = (float)(p64[2] + ref[2] + mz * inv);
             A.flags[orig] = (uint8_t)flags;
             A.loc[self] = make_loc((uint32_t)A.tier, slot);
         }
+        return true;
     }
 
     __device__ void write_empty(uint32_t orig, uint32_t extra) {
@@ -883,34 +979,67 @@ __global__ __launch_bounds__(64 * WAVES) void k_clip(ClipArgs A) {
         const uint32_t k = A.list ? A.list[c] : c;
         const uint32_t slot = A.list ? c : k;
         const uint32_t orig = A.order[k];
-        if (!C.init(k)) {
-            C.write_empty(orig, 0);
-            ++st_empty;
-            continue;
-        }
-        if (A.tier > 0) C.flags |= kFlagLarge;
-        int r = C.traverse();
-        if (r == kOverflow) {
-            if (A.next_list) {
-                if (C.ln == 0) A.next_list[atomicAdd(A.next_count, 1u)] = k;
-            } else {
-                C.write_empty(orig, kFlagFailed);
-                ++st_fail;
-                ++st_empty;
+        // a cell is built with plain FP32 signs first (mixed mode: with FP64
+        // re-evaluation of doubtful ones); if that meets an inconsistent
+        // configuration it is rebuilt once with the FP64 re-evaluation
+        C.robust = A.precision == 2 ? 1 : 0;
+        bool done = false, escalated = false, loser = false;
+        for (int attempt = 0; attempt < 3 && !done; ++attempt) {
+            if (!C.init(k)) {
+                loser = true;
+                break;
             }
-            continue;
+            if (attempt > 0) C.flags |= kFlagFP64;
+            if (A.tier > 0) C.flags |= kFlagLarge;
+            int r = C.traverse();
+            if (r == kRestart) {
+                C.robust = C.robust + 1;
+                continue;
+            }
+            if (r == kOverflow) {
+                if (A.next_list) {
+                    if (C.ln == 0) A.next_list[atomicAdd(A.next_count, 1u)] = k;
+                    escalated = true;
+                } else {
+                    C.write_empty(orig, kFlagFailed);
+                    ++st_fail;
+                    ++st_empty;
+                }
+                done = true;
+                break;
+            }
+            if (r == kEmptied) {
+                C.write_empty(orig, 0);
+                ++st_empty;
+                done = true;
+            } else if (C.finalize(slot, orig)) {
+                done = true;
+            } else if (C.robust < 2) {
+                C.robust = C.robust + 1;
+            } else {
+                break;
+            }
         }
-        if (r == kEmptied) {
+        if (loser) {
             C.write_empty(orig, 0);
             ++st_empty;
-        } else {
-            C.finalize(slot, orig);
+            continue;
+        }
+        if (escalated) continue;
+        if (!done) {
+            // still inconsistent after the robust rebuild: report an empty cell
+            C.write_empty(orig, kFlagFailed | kFlagUncertain);
+            ++st_fail;
+            ++st_empty;
         }
         st_large += (C.flags & kFlagLarge) ? 1 : 0;
         st_unc += (C.flags & kFlagUncertain) ? 1 : 0;
         st_fp64 += (C.flags & kFlagFP64) ? 1 : 0;
     }
     if (C.ln == 0) {
+        if (C.counting)
+            for (int c = 0; c < kCtrCount; ++c)
+                if (C.ctr[c]) atomicAdd(&A.ctr[c], (unsigned long long)C.ctr[c]);
         if (st_empty) atomicAdd(&A.stats[kStatEmpty], st_empty);
         if (st_large) atomicAdd(&A.stats[kStatLarge], st_large);
         if (st_unc) atomicAdd(&A.stats[kStatUncertain], st_unc);

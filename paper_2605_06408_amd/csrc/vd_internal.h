@@ -65,6 +65,9 @@ constexpr uint32_t kFlagEmpty = 1u, kFlagFP64 = 2u, kFlagLarge = 4u, kFlagUncert
 
 // Build statistics accumulated by the clip kernels (device, uint64 each).
 enum StatIndex { kStatEmpty = 0, kStatLarge, kStatUncertain, kStatFailed, kStatFP64, kStatCount };
+// Work counters (mirror VD_CTR_* in vd.h).
+enum CtrIndex { kCtrClassify = 0, kCtrNewVertex, kCtrNode, kCtrSite, kCtrFinal, kCtrClip, kCtrEffective, kCtrLeaf,
+                kCtrCount };
 
 struct ClipArgs {
     const float4* pts;        // sites in Morton order: x, y, z, w (w = -inf: coincident loser)
@@ -93,6 +96,7 @@ struct ClipArgs {
     float* cen;               // [3n]
     uint8_t* flags;           // [n]
     unsigned long long* stats;  // [kStatCount]
+    unsigned long long* ctr;    // [kCtrCount] work counters, or null
 };
 
 struct WriteArgs {

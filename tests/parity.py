@@ -83,7 +83,11 @@ def _canon_gpu(g, t):
     verts = {k: g["vert"][v0 + j].astype(np.float64) for j, k in enumerate(keys)}
     facets = {}
     for f in range(g["facet_off"][t], g["facet_off"][t + 1]):
-        ring = [keys[int(x) - v0] for x in g["fv"][g["fv_off"][f]:g["fv_off"][f + 1]]]
+        idx = [int(x) - v0 for x in g["fv"][g["fv_off"][f]:g["fv_off"][f + 1]]]
+        if not idx or min(idx) < 0 or max(idx) >= len(keys):
+            facets[int(g["facet_nbr"][f])] = ("malformed",)
+            continue
+        ring = [keys[q] for q in idx]
         r = min(range(len(ring)), key=lambda q: ring[q])
         facets[int(g["facet_nbr"][f])] = tuple(ring[r:] + ring[:r])
     nbr = [int(x) for x in g["nbr"][g["nbr_off"][t]:g["nbr_off"][t + 1]]]
@@ -101,6 +105,22 @@ def _canon_oracle(o, t):
         facets[int(o["facet_code"][f])] = tuple(ring[r:] + ring[:r])
     nbr = [int(x) for x in o["nbr"][o["nbr_off"][t]:o["nbr_off"][t + 1]]]
     return nbr, verts, facets, len(keys)
+
+
+def _poly_volume(verts: dict, facets: dict) -> float:
+    """Volume of a closed polytope from its facet rings (FP64 fan)."""
+    keys = list(verts)
+    ref = verts[keys[0]]
+    v6 = 0.0
+    for ring in facets.values():
+        if ring and ring[0] == "malformed":
+            return float("nan")
+        a = verts[ring[0]] - ref
+        for t in range(1, len(ring) - 1):
+            b = verts[ring[t]] - ref
+            c = verts[ring[t + 1]] - ref
+            v6 += float(np.dot(a, np.cross(b, c)))
+    return v6 / 6.0
 
 
 def compare(g: dict, o: dict, tau: float = 1e-5, tol: float = 1e-5, max_report: int = 5) -> dict:
@@ -123,8 +143,10 @@ def compare(g: dict, o: dict, tau: float = 1e-5, tol: float = 1e-5, max_report: 
         rep["certified"] += 1
         if not same:
             if len(rep["topo_fail"]) < max_report:
-                rep["topo_fail"].append(dict(cell=int(g["ids"][t]), gpu_empty=ge, oracle_empty=oe,
-                                             gpu_nbr=gn, oracle_nbr=on, margin=float(o["margin"][t])))
+                rep["topo_fail"].append(dict(cell=int(g["ids"][t]), gpu_flags=int(g["flags"][t]), oracle_empty=oe,
+                                             only_gpu=sorted(set(gn) - set(on)), only_oracle=sorted(set(on) - set(gn)),
+                                             nbr_equal=gn == on, verts_equal=set(gv) == set(ov),
+                                             margin=float(o["margin"][t])))
             else:
                 rep["topo_fail"].append(int(g["ids"][t]))
             continue
@@ -141,7 +163,10 @@ def compare(g: dict, o: dict, tau: float = 1e-5, tol: float = 1e-5, max_report: 
         rep["max_cen_err"] = max(rep["max_cen_err"], ce)
         if ve > tol or vv > tol or ce > tol:
             if len(rep["geo_fail"]) < max_report:
-                rep["geo_fail"].append(dict(cell=int(g["ids"][t]), vert=ve, vol=vv, cen=ce))
+                rep["geo_fail"].append(dict(cell=int(g["ids"][t]), vert=ve, vol=vv, cen=ce,
+                                            gpu_vol=float(g["vol"][t]), oracle_vol=float(o["vol"][t]),
+                                            gpu_vol_from_own_vertices=_poly_volume(gv, gf),
+                                            gpu_flags=int(g["flags"][t]), nv=len(gv)))
     return rep
 
 

@@ -58,5 +58,5 @@ def test_null_arguments_are_rejected_on_the_host(lib):
 def test_struct_layouts_match_header():
     import paper_2605_06408_amd as vd
     assert ctypes.sizeof(vd.Options) == 32
-    assert ctypes.sizeof(vd.Sizes) == 80
+    assert ctypes.sizeof(vd.Sizes) == 88
     assert ctypes.sizeof(vd.Outputs) == 12 * 8
