@@ -37,6 +37,8 @@ def _losers(xyz, w):
 
 
 def _planes(xyz, w, box, i):
+    import numpy as np
+    box = [float(np.float32(v)) for v in box]  # the clip box is an FP32 input
     p = [Q(float(c)) for c in xyz[i]]
     wi = Q(float(w[i])) if w is not None else Q(0)
     pl = []
