@@ -35,7 +35,9 @@ METRIC = "cells/sec at 1M and 20M sites (Voronoi, power); fwd+bwd cells/sec"
 #   site_test    difference (3), |a|^2 (5), b (2), octant radius (5),
 #                rounding slack and squared compare (10)                     = 25
 #   final_vertex three fan tetrahedra: cross (9), dot (5), moment (6) each   = 60
-FLOPS_PER_UNIT = {"classify": 7, "new_vertex": 51, "node_test": 32, "site_test": 25, "final_vertex": 60}
+#   ball_test    point-to-box distance (12), vertex power (5), compare (3)  = 20
+FLOPS_PER_UNIT = {"classify": 7, "new_vertex": 51, "node_test": 32, "site_test": 25, "final_vertex": 60,
+                  "ball_test": 20}
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (256 CUs x 2.4 GHz, packed FMA)
 PEAK_HBM_GBS = 8000.0
 
@@ -51,7 +53,7 @@ def parse():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", type=int, default=1, help="1 fp32, 2 mixed fp32/fp64")
     ap.add_argument("--leaf-size", type=int, default=0)
-    ap.add_argument("--culling", type=int, default=1)
+    ap.add_argument("--culling", type=int, default=3)
     ap.add_argument("--traversal", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
@@ -82,6 +84,10 @@ def cpu_baseline(xyz, w, box, seconds: float) -> dict:
                       % (m, n, dt)}
 
 
+def log(msg: str):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -93,8 +99,10 @@ def main():
     import paper_2605_06408_amd as vd
     from paper_2605_06408_amd import workloads as wl
 
+    log("generating %s" % args.config)
     xyz, w, box = wl.make(args.config, args.seed, args.n)
     n = len(xyz)
+    log("generated n=%d" % n)
     dev = torch.device("cuda", 0)
     tx = torch.from_numpy(xyz).to(dev)
     tw = None if w is None else torch.from_numpy(w).to(dev)
@@ -110,14 +118,16 @@ def main():
     step(counters=True)
     torch.cuda.synchronize()
     ctr = ctx.counters()
+    log("counted build done")
     for _ in range(args.warmup):
         d = step(profile=True)
     torch.cuda.synchronize()
     clip_ms, phases = [], {k: 0.0 for k in vd.PHASES}
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for k in range(args.steps):
         d = step(profile=True)
         tm = ctx.timings()
+        log("step %d: %.1f ms build" % (k, tm["build"]))
         clip_ms.append(tm["clip"])
         for k in phases:
             phases[k] += tm[k] / args.steps
@@ -126,7 +136,8 @@ def main():
     ms = (t1 - t0) * 1000.0 / args.steps
     sizes = d.sizes
 
-    flops = sum(ctr[k] * FLOPS_PER_UNIT[k] for k in FLOPS_PER_UNIT)
+    # the roofline prices the 64-vertex kernel alone, with its own counters
+    flops = sum(ctr["tier0"][k] * FLOPS_PER_UNIT[k] for k in FLOPS_PER_UNIT)
     clip_s = float(np.mean(clip_ms)) / 1000.0
     achieved = flops / clip_s / 1e12
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
@@ -147,6 +158,7 @@ def main():
         "sizes": sizes,
     }
     if not args.no_cpu_baseline:
+        log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(xyz, w, box, args.cpu_seconds)
     print(json.dumps(out))
 

@@ -55,7 +55,9 @@ typedef enum {
 typedef struct vd_options {
     int32_t precision;  /* 1 = FP32 predicates (default), 2 = mixed FP32 / FP64 */
     int32_t leaf_size;  /* sites per BVH leaf, 1..64 (default 16) */
-    int32_t culling;    /* 1 = directional (Sec. 4.2.1, default), 2 = isotropic radius */
+    int32_t culling;    /* 1 = directional (Sec. 4.2.1-4.2.2), 2 = isotropic radius,
+                           3 = directional plus vertex power-ball node test and
+                               exact plane-versus-cell-box site test (default) */
     int32_t traversal;  /* 1 = best-first (Alg. 1, default), 2 = depth-first */
     int32_t profile;    /* 1 = record per-phase HIP-event timings (vd_get_timings) */
     int32_t counters;   /* 1 = count the method's work units (vd_get_counters) */
@@ -72,7 +74,9 @@ typedef struct vd_options {
 #define VD_PHASE_CLIP_TIER1 6 /* the 256-vertex tier alone (part of VD_PHASE_CLIP_LARGE) */
 #define VD_PHASE_COUNT 7
 
-/* Work units counted when vd_options.counters = 1 (whole build, all tiers). */
+/* Work units counted when vd_options.counters = 1.  vd_get_counters returns
+ * them per capacity tier: entry k + VD_CTR_COUNT * t is unit k of tier t
+ * (t = 0: 64 vertices, 1: 256, 2: 1024). */
 #define VD_CTR_CLASSIFY 0     /* vertex-versus-plane side tests */
 #define VD_CTR_NEW_VERTEX 1   /* vertices created by clipping */
 #define VD_CTR_NODE_TEST 2    /* BVH child-box tests (Sec. 4.2.2) */
@@ -81,7 +85,8 @@ typedef struct vd_options {
 #define VD_CTR_CLIP 5         /* clip attempts (candidate planes that passed the tests) */
 #define VD_CTR_CLIP_EFFECTIVE 6 /* clips that changed the cell */
 #define VD_CTR_LEAF 7         /* leaves visited */
-#define VD_CTR_COUNT 8
+#define VD_CTR_BALL 8         /* vertex-versus-node-box power-ball tests (culling 3) */
+#define VD_CTR_COUNT 9
 
 /* Result sizes of the last vd_build. */
 typedef struct vd_sizes {
@@ -168,7 +173,8 @@ VD_API vd_status vd_get_sizes(const vd_context* ctx, vd_sizes* sizes);
  * vd_options.profile = 1 on that build.  Waits for the recorded events. */
 VD_API vd_status vd_get_timings(vd_context* ctx, float* ms, int32_t count);
 
-/* Work counters of the last build, out[VD_CTR_*]; needs vd_options.counters = 1. */
+/* Work counters of the last build (up to 3 * VD_CTR_COUNT entries, see
+ * VD_CTR_*); needs vd_options.counters = 1. */
 VD_API vd_status vd_get_counters(const vd_context* ctx, uint64_t* out, int32_t count);
 
 /* Message for the last error on this thread ("" if none). */

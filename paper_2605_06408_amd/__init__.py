@@ -29,13 +29,15 @@ PRECISION_FP32 = 1
 PRECISION_MIXED = 2
 CULLING_DIRECTIONAL = 1
 CULLING_ISOTROPIC = 2
+CULLING_BALLS = 3
 TRAVERSAL_BEST_FIRST = 1
 TRAVERSAL_DEPTH_FIRST = 2
 
 MAX_SITES = 1 << 25
 
 PHASES = ("lbvh", "clip", "clip_large", "scan", "build", "write", "clip_tier1")
-COUNTERS = ("classify", "new_vertex", "node_test", "site_test", "final_vertex", "clip", "clip_effective", "leaf")
+COUNTERS = ("classify", "new_vertex", "node_test", "site_test", "final_vertex", "clip", "clip_effective", "leaf",
+            "ball_test")
 
 STATUS = {0: "VD_OK", 1: "VD_ERR_INVALID_ARG", 2: "VD_ERR_HIP", 3: "VD_ERR_OOM", 4: "VD_ERR_STATE",
           5: "VD_ERR_CAPACITY"}
@@ -148,7 +150,7 @@ class Context:
             pass
 
     def build_sizes(self, xyz, w=None, bbox=None, precision=PRECISION_FP32, leaf_size=0,
-                    culling=CULLING_DIRECTIONAL, traversal=TRAVERSAL_BEST_FIRST, allow_failed=False,
+                    culling=CULLING_BALLS, traversal=TRAVERSAL_BEST_FIRST, allow_failed=False,
                     profile=False, counters=False) -> Sizes:
         """Run vd_build only (the diagram stays in the context)."""
         import torch
@@ -206,10 +208,15 @@ class Context:
         return dict(zip(PHASES, [float(x) for x in ms]))
 
     def counters(self) -> dict:
-        """Work counters of the last build made with counters=True."""
-        v = (ctypes.c_uint64 * len(COUNTERS))()
-        _check(self.lib.vd_get_counters(self.handle, v, len(COUNTERS)), "vd_get_counters")
-        return dict(zip(COUNTERS, [int(x) for x in v]))
+        """Work counters of the last build made with counters=True: a dict per
+        capacity tier ("tier0", "tier1", "tier2") and their sum ("total")."""
+        k = len(COUNTERS)
+        v = (ctypes.c_uint64 * (3 * k))()
+        _check(self.lib.vd_get_counters(self.handle, v, 3 * k), "vd_get_counters")
+        vals = [int(x) for x in v]
+        out = {"tier%d" % t: dict(zip(COUNTERS, vals[t * k:(t + 1) * k])) for t in range(3)}
+        out["total"] = {c: sum(out["tier%d" % t][c] for t in range(3)) for c in COUNTERS}
+        return out
 
     def build(self, xyz, w=None, bbox=None, **kw) -> Diagram:
         sz = self.build_sizes(xyz, w, bbox, **kw)

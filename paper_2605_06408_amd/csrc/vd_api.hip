@@ -179,12 +179,12 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     if (opt) o = *opt;
     if (o.precision == 0) o.precision = 1;
     if (o.leaf_size == 0) o.leaf_size = vd::kDefaultLeaf;
-    if (o.culling == 0) o.culling = 1;
+    if (o.culling == 0) o.culling = 3;
     if (o.traversal == 0) o.traversal = 1;
     if (o.precision < 1 || o.precision > 2) return fail(VD_ERR_INVALID_ARG, "vd_build: precision must be 1 or 2");
     if (o.leaf_size < 1 || o.leaf_size > vd::kMaxLeaf)
         return fail(VD_ERR_INVALID_ARG, "vd_build: leaf_size must be in [1, 64]");
-    if (o.culling < 1 || o.culling > 2) return fail(VD_ERR_INVALID_ARG, "vd_build: culling must be 1 or 2");
+    if (o.culling < 1 || o.culling > 3) return fail(VD_ERR_INVALID_ARG, "vd_build: culling must be 1, 2 or 3");
     if (o.traversal < 1 || o.traversal > 2) return fail(VD_ERR_INVALID_ARG, "vd_build: traversal must be 1 or 2");
     if (bbox) {
         for (int k = 0; k < 6; ++k)
@@ -234,14 +234,14 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     VD_TRY(ensure(c->list1, N * sizeof(uint32_t)));
     VD_TRY(ensure(c->list2, N * sizeof(uint32_t)));
     VD_TRY(ensure(c->stats, vd::kStatCount * sizeof(unsigned long long)));
-    VD_TRY(ensure(c->ctr, vd::kCtrCount * sizeof(unsigned long long)));
+    VD_TRY(ensure(c->ctr, 3 * vd::kCtrCount * sizeof(unsigned long long)));
     VD_TRY(ensure_stage(c, 0, n));
 
     // misc: [0] error bits, [1..3] work counters, [4] tier-1 list count, [5] tier-2 list count
     uint32_t* misc = as<uint32_t>(c->misc);
     if (prof) VD_HIP(hipEventRecord(c->ev[0], s));
     VD_HIP(hipMemsetAsync(misc, 0, 16 * sizeof(uint32_t), s));
-    if (o.counters) VD_HIP(hipMemsetAsync(c->ctr.p, 0, vd::kCtrCount * sizeof(unsigned long long), s));
+    if (o.counters) VD_HIP(hipMemsetAsync(c->ctr.p, 0, 3 * vd::kCtrCount * sizeof(unsigned long long), s));
     VD_HIP(hipMemsetAsync(c->stats.p, 0, vd::kStatCount * sizeof(unsigned long long), s));
     float4* pts = as<float4>(c->pts);
     float* dbbox = as<float>(c->bbox);
@@ -327,6 +327,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
         a.next_list = tier == 1 ? as<uint32_t>(c->list2) : nullptr;
         a.next_count = tier == 1 ? misc + 5 : nullptr;
         a.stage = stage_of(c, tier);
+        if (a.ctr) a.ctr = as<unsigned long long>(c->ctr) + tier * vd::kCtrCount;
         int waves = vd::clip_grid_waves(tier, c->num_cu);
         if ((int64_t)waves > (int64_t)cnt) waves = (int)cnt;
         VD_HIP(vd::launch_clip(a, waves, s));
@@ -442,9 +443,9 @@ VD_API vd_status vd_get_timings(vd_context* c, float* ms, int32_t count) {
 VD_API vd_status vd_get_counters(const vd_context* c, uint64_t* out, int32_t count) {
     if (!c || !out || count < 0) return fail(VD_ERR_INVALID_ARG, "vd_get_counters: bad argument");
     if (!c->valid || !c->counted) return fail(VD_ERR_STATE, "vd_get_counters: last build did not count");
-    unsigned long long h[vd::kCtrCount];
+    unsigned long long h[3 * vd::kCtrCount];
     VD_HIP(hipMemcpy(h, c->ctr.p, sizeof(h), hipMemcpyDeviceToHost));
-    for (int k = 0; k < count && k < vd::kCtrCount; ++k) out[k] = (uint64_t)h[k];
+    for (int k = 0; k < count && k < 3 * vd::kCtrCount; ++k) out[k] = (uint64_t)h[k];
     return VD_OK;
 }
 

@@ -124,7 +124,9 @@ struct Cell {
     uint32_t vt[VPL], va[VPL];
     uint64_t alive[VPL];
     int np;
-    // bounds of the current cell (uniform)
+    // bounds of the current cell (uniform): AABB in the site's frame, the
+    // squared far-corner coordinates, the directional and isotropic radii
+    float blo0, blo1, blo2, bhi0, bhi1, bhi2;
     float hx2, hy2, hz2, lx2, ly2, lz2, rmax2, riso2;
     // queue (one entry per lane and slot)
     uint32_t qe[VPL];
@@ -199,6 +201,8 @@ struct Cell {
         float l0 = wmin(mn0), l1 = wmin(mn1), l2 = wmin(mn2);
         float h0 = wmax(mx0), h1 = wmax(mx1), h2 = wmax(mx2);
         riso2 = wmax(r2);
+        blo0 = l0; blo1 = l1; blo2 = l2;
+        bhi0 = h0; bhi1 = h1; bhi2 = h2;
         hx2 = h0 * h0; hy2 = h1 * h1; hz2 = h2 * h2;
         lx2 = l0 * l0; ly2 = l1 * l1; lz2 = l2 * l2;
         rmax2 = fmaxf(hx2, lx2) + fmaxf(hy2, ly2) + fmaxf(hz2, lz2);
@@ -209,6 +213,42 @@ struct Cell {
     __device__ __forceinline__ float radius2_toward(float ax, float ay, float az) const {
         if (A.culling == 2) return riso2;
         return (ax >= 0.f ? hx2 : lx2) + (ay >= 0.f ? hy2 : ly2) + (az >= 0.f ? hz2 : lz2);
+    }
+
+    // Power-ball test of a node box (frame of the site): a site p_j in the box
+    // with w_j <= wmax cuts the cell only if some vertex v has
+    // |v - p_j|^2 - w_j < |v|^2 - w_i, and |v - p_j|^2 >= dist(v, box)^2.
+    // Returns true if some vertex might be cut (the box cannot be skipped).
+    __device__ bool ball_hit(float lx, float ly, float lz, float hx, float hy, float hz, float wm) {
+        if (counting) {
+            uint64_t nal = 0;
+#pragma unroll
+            for (int s = 0; s < VPL; ++s) nal += (uint64_t)popc(alive[s]);
+            count(kCtrBall, nal);
+        }
+        bool hit = false;
+#pragma unroll
+        for (int s = 0; s < VPL; ++s) {
+            if ((alive[s] >> ln) & 1) {
+                float dx = fmaxf(fmaxf(lx - y0[s], y0[s] - hx), 0.f);
+                float dy = fmaxf(fmaxf(ly - y1[s], y1[s] - hy), 0.f);
+                float dz = fmaxf(fmaxf(lz - y2[s], y2[s] - hz), 0.f);
+                float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                float r2 = fmaf(y0[s], y0[s], fmaf(y1[s], y1[s], y2[s] * y2[s]));
+                float lhs = d2 - wm, rhs = r2 - pw;
+                hit |= lhs - rhs <= 16.f * kU * (d2 + r2 + fabsf(wm) + fabsf(pw));
+            }
+        }
+        return ballot(hit) != 0;
+    }
+
+    // Broadcasts child record lanes' boxes and applies the ball test to the
+    // child held by lane `l` (its box relative to the site).
+    __device__ bool ball_hit_lane(const NodeChild& c, int l) {
+        float lx = rdl(c.lo[0] - px, l), ly = rdl(c.lo[1] - py, l), lz = rdl(c.lo[2] - pz, l);
+        float hx = rdl(c.hi[0] - px, l), hy = rdl(c.hi[1] - py, l), hz = rdl(c.hi[2] - pz, l);
+        float wm = rdl(c.wmax, l);
+        return ball_hit(lx, ly, lz, hx, hy, hz, wm);
     }
 
     // ------------------------------------------------------------ FP64 side test
@@ -675,6 +715,13 @@ struct Cell {
         }
         auto keep = [&](bool c) -> bool {
             if (!c) return false;
+            if (A.culling == 3) {
+                // the plane misses the cell's AABB: max over the box of a.y <= b
+                float cx = ax >= 0.f ? bhi0 : blo0, cy = ay >= 0.f ? bhi1 : blo1, cz = az >= 0.f ? bhi2 : blo2;
+                float m = fmaf(ax, cx, fmaf(ay, cy, az * cz));
+                float slack = 8.f * kU * (fabsf(ax * cx) + fabsf(ay * cy) + fabsf(az * cz) + a2 + fabsf(dw));
+                return m > b - slack;
+            }
             float r2 = radius2_toward(ax, ay, az);
             float t = b - 4.f * kU * (2.f * a2 + fabsf(dw) + r2);
             return !(t > 0.f && t * t > a2 * r2);
@@ -732,7 +779,13 @@ struct Cell {
                     node_test(c, &key, &cull, &delta);
                     ref = c.ref;
                 }
-                const bool c0 = rdl((int)cull, 0) != 0, c1 = rdl((int)cull, 1) != 0;
+                bool c0 = rdl((int)cull, 0) != 0, c1 = rdl((int)cull, 1) != 0;
+                if (A.culling == 3) {
+                    NodeChild cc;
+                    if (ln < 2) load_child(node, (int)ln, &cc);
+                    if (!c0 && !ball_hit_lane(cc, 0)) c0 = true;
+                    if (!c1 && !ball_hit_lane(cc, 1)) c1 = true;
+                }
                 if (c0 && c1) {
                     have = false;
                     break;
@@ -766,13 +819,15 @@ struct Cell {
                 float key = 0.f, delta = 0.f;
                 bool cull = true;
                 uint32_t ref = 0;
+                NodeChild c;
                 if (ln == 0) {
-                    NodeChild c;
                     load_child(e >> 1, (int)(e & 1), &c);
                     node_test(c, &key, &cull, &delta);
                     ref = c.ref;
                 }
-                if (!rdl((int)cull, 0)) {
+                bool culled = rdl((int)cull, 0) != 0;
+                if (!culled && A.culling == 3 && !ball_hit_lane(c, 0)) culled = true;
+                if (!culled) {
                     cur = rdl(ref, 0);
                     have = true;
                     break;

@@ -67,7 +67,7 @@ constexpr uint32_t kFlagEmpty = 1u, kFlagFP64 = 2u, kFlagLarge = 4u, kFlagUncert
 enum StatIndex { kStatEmpty = 0, kStatLarge, kStatUncertain, kStatFailed, kStatFP64, kStatCount };
 // Work counters (mirror VD_CTR_* in vd.h).
 enum CtrIndex { kCtrClassify = 0, kCtrNewVertex, kCtrNode, kCtrSite, kCtrFinal, kCtrClip, kCtrEffective, kCtrLeaf,
-                kCtrCount };
+                kCtrBall, kCtrCount };
 
 struct ClipArgs {
     const float4* pts;        // sites in Morton order: x, y, z, w (w = -inf: coincident loser)

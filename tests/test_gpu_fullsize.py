@@ -1,0 +1,76 @@
+"""Full-size workloads (1M and 20M sites), built whole on the GPU in the
+configuration bench.py times.  The oracle checks a sample of cells one by one
+(random cells, cells of the larger-capacity passes, empty cells); the whole
+diagram is checked against invariants that hold at any size: volumes sum to
+the box volume and the neighbour relation is symmetric."""
+import numpy as np
+import pytest
+
+from paper_2605_06408_amd import workloads as wl
+
+from .parity import assert_parity, compare, gpu_build, to_numpy
+
+pytestmark = pytest.mark.gpu
+
+
+def _sample(d, n, rng, k_random=200, k_large=60, k_empty=20):
+    flags = d.flags.cpu().numpy()
+    ids = set(rng.choice(n, min(n, k_random), replace=False).tolist())
+    large = np.nonzero(flags & 4)[0]
+    if len(large):
+        ids |= set(rng.choice(large, min(len(large), k_large), replace=False).tolist())
+    empty = np.nonzero(flags & 1)[0]
+    if len(empty):
+        ids |= set(rng.choice(empty, min(len(empty), k_empty), replace=False).tolist())
+    return np.array(sorted(ids), np.int64)
+
+
+def _invariants(oracle_mod, d, xyz, w, box, tau=1e-5):
+    """Volumes sum to the box volume; the neighbour relation is symmetric except
+    where a cell is too close to a degeneracy for FP32 to decide (every
+    asymmetric pair must contain a cell the oracle does not certify)."""
+    import torch
+    bvol = float(np.prod(np.asarray(box[3:], float) - np.asarray(box[:3], float)))
+    total = float(d.vol.double().sum().item())
+    assert total == pytest.approx(bvol, rel=1e-5)
+    n = d.vol.shape[0]
+    rows = torch.repeat_interleave(torch.arange(n, device=d.nbr.device), d.nbr_off[1:] - d.nbr_off[:-1])
+    cols = d.nbr.to(torch.int64)
+    fwd = rows * n + cols
+    rev = cols * n + rows
+    missing = fwd[~torch.isin(fwd, rev)]  # (i, j) listed by i but not by j
+    pairs = torch.stack([missing // n, missing % n], 1).cpu().numpy()
+    print("asymmetric pairs: %d of %d" % (len(pairs), len(fwd)))
+    assert len(pairs) <= 1e-4 * len(fwd)
+    if len(pairs):
+        cells = np.unique(pairs.ravel())
+        o = oracle_mod.cells(xyz, w, box, ids=cells)
+        m = dict(zip(cells.tolist(), o["margin"].tolist()))
+        for i, j in pairs.tolist():
+            assert min(m[i], m[j]) < tau, (i, j, m[i], m[j])
+    assert d.sizes["n_failed"] == 0
+
+
+@pytest.mark.parametrize("name", ["clustered_1m", "power_uniform_1m", "power_clustered_1m"])
+def test_one_million(oracle_mod, name):
+    xyz, w, box = wl.make(name, 0)
+    d = gpu_build(xyz, w, box)
+    _invariants(oracle_mod, d, xyz, w, box)
+    ids = _sample(d, len(xyz), np.random.default_rng(1))
+    g = to_numpy(d, ids)
+    o = oracle_mod.cells(xyz, w, box, ids=ids)
+    rep = compare(g, o)
+    rep["sizes"] = d.sizes
+    assert_parity(rep, 0.8)
+
+
+def test_surface_twenty_million(oracle_mod):
+    xyz, w, box = wl.make("surface_20m", 0)
+    d = gpu_build(xyz, w, box)
+    _invariants(oracle_mod, d, xyz, w, box)
+    ids = _sample(d, len(xyz), np.random.default_rng(2), k_random=120, k_large=40, k_empty=0)
+    g = to_numpy(d, ids)
+    o = oracle_mod.cells(xyz, w, box, ids=ids)
+    rep = compare(g, o)
+    rep["sizes"] = d.sizes
+    assert_parity(rep, 0.8)
