@@ -41,6 +41,31 @@ FLOPS_PER_UNIT = {"classify": 7, "new_vertex": 51, "node_test": 32, "site_test":
 PEAK_FP32_TFLOPS = 157.3   # MI355X FP32 vector peak (256 CUs x 2.4 GHz, packed FMA)
 PEAK_HBM_GBS = 8000.0
 
+# HBM traffic of the 64-vertex clip kernel per launch, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of bench.py on the named
+# workload, each scaled by what the same counter reads for a plain 256 MiB
+# device copy in the same run (FETCH_SIZE 131088.7 KiB -> x2.0, WRITE_SIZE
+# 262144.0 KiB -> x1.0).  Valid only while the kernel source is unchanged.
+TRAFFIC_MEASURED = {
+    "sources_sha1": {"paper_2605_06408_amd/csrc/vd_clip.hip": "734cd0f1444d1abcfc30103b2f247039312bb772",
+                     "paper_2605_06408_amd/csrc/vd_internal.h": "2e209136d06e205eb0832a129b55eeb2a51a943f"},
+    "workload": "clustered_1m", "fetch_kib": 139334.6, "write_kib": 908202.3, "fetch_scale": 2.0, "write_scale": 1.0,
+}
+
+
+def measured_traffic(workload: str):
+    """Bytes per launch of the clip kernel, or None if not measured for this
+    workload or the kernel changed since."""
+    import hashlib
+    t = TRAFFIC_MEASURED
+    if t["workload"] != workload:
+        return None
+    for rel, sha in t["sources_sha1"].items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha1(f.read()).hexdigest() != sha:
+                return None
+    return 1024.0 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"])
+
 
 def parse():
     ap = argparse.ArgumentParser(description=__doc__)
@@ -57,6 +82,8 @@ def parse():
     ap.add_argument("--traversal", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run one plain 256 MiB device copy (reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -68,11 +95,17 @@ def cpu_baseline(xyz, w, box, seconds: float) -> dict:
     n = len(xyz)
     rng = np.random.default_rng(12345)
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or (os.cpu_count() or 1)
-    m0 = min(n, max(threads, 32))
-    ids = np.sort(rng.choice(n, m0, replace=False))
-    t0 = time.perf_counter()
-    oracle.cells(xyz, w, box, ids=ids, threads=threads)
-    dt = time.perf_counter() - t0
+    # calibrate on growing samples until one takes >= 1 s, then size the
+    # measured sample for about `seconds` of work
+    m0 = min(n, 16 * threads)
+    while True:
+        ids = np.sort(rng.choice(n, m0, replace=False))
+        t0 = time.perf_counter()
+        oracle.cells(xyz, w, box, ids=ids, threads=threads)
+        dt = time.perf_counter() - t0
+        if dt >= 1.0 or m0 >= n:
+            break
+        m0 = min(n, m0 * 4)
     rate = m0 / max(dt, 1e-9)
     m = int(min(n, max(m0, rate * seconds)))
     ids = np.sort(rng.choice(n, m, replace=False))
@@ -103,6 +136,12 @@ def main():
     xyz, w, box = wl.make(args.config, args.seed, args.n)
     n = len(xyz)
     log("generated n=%d" % n)
+    if args.copy_calibration:
+        src = torch.ones(64 << 20, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     dev = torch.device("cuda", 0)
     tx = torch.from_numpy(xyz).to(dev)
     tw = None if w is None else torch.from_numpy(w).to(dev)
@@ -140,8 +179,9 @@ def main():
     flops = sum(ctr["tier0"][k] * FLOPS_PER_UNIT[k] for k in FLOPS_PER_UNIT)
     clip_s = float(np.mean(clip_ms)) / 1000.0
     achieved = flops / clip_s / 1e12
+    traffic = measured_traffic(args.config)
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
-                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": None,
+                "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
                 "kernel": "k_clip<1,4> (64-vertex tier)", "kernel_ms": clip_s * 1000.0,
                 "flops_per_launch": flops}
 
