@@ -67,7 +67,7 @@ typedef struct vd_options {
 /* Phases reported by vd_get_timings (milliseconds, HIP events on `stream`). */
 #define VD_PHASE_LBVH 0       /* packing, Morton codes, radix sort, tree, bounds */
 #define VD_PHASE_CLIP 1       /* traversal + clipping, 64-vertex tier (one kernel) */
-#define VD_PHASE_CLIP_LARGE 2 /* traversal + clipping, 256- and 1024-vertex tiers */
+#define VD_PHASE_CLIP_LARGE 2 /* traversal + clipping, 256- and 16384-vertex tiers */
 #define VD_PHASE_SCAN 3       /* prefix sums of the per-cell counts */
 #define VD_PHASE_BUILD 4      /* the whole vd_build, first to last device operation */
 #define VD_PHASE_WRITE 5      /* vd_write (CSR write-out and copies) */
@@ -76,7 +76,7 @@ typedef struct vd_options {
 
 /* Work units counted when vd_options.counters = 1.  vd_get_counters returns
  * them per capacity tier: entry k + VD_CTR_COUNT * t is unit k of tier t
- * (t = 0: 64 vertices, 1: 256, 2: 1024). */
+ * (t = 0: 64 vertices, 1: 256, 2: 16384). */
 #define VD_CTR_CLASSIFY 0     /* vertex-versus-plane side tests */
 #define VD_CTR_NEW_VERTEX 1   /* vertices created by clipping */
 #define VD_CTR_NODE_TEST 2    /* BVH child-box tests (Sec. 4.2.2) */
@@ -100,7 +100,7 @@ typedef struct vd_sizes {
     int64_t n_uncertain;/* cells flagged VD_FLAG_UNCERTAIN */
     int64_t n_failed;   /* cells flagged VD_FLAG_FAILED (status VD_ERR_CAPACITY) */
     int64_t n_fp64;     /* cells with at least one FP64 re-evaluation */
-    int64_t n_huge;     /* cells that needed the 1024-vertex pass */
+    int64_t n_huge;     /* cells that needed the 16384-vertex pass */
 } vd_sizes;
 
 /* Output arrays: caller-owned device memory, sized from vd_sizes.  Rows are

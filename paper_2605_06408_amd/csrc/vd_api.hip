@@ -35,7 +35,8 @@ struct vd_context {
     // grow-only device scratch
     DevBuf pts, spts, keys[2], vals[2], inv, mark, child, pint, pleaf, range, counters, nodes, hist, stmp, bbox,
         bpart, misc, loc, cnt_v, cnt_f, cnt_n, vol, cen, flags, offv, offf, offn, scan_tmp, list1, list2, stats, ctr;
-    DevBuf st_vert[3], st_code[3], st_fsize[3], st_fv[3];
+    DevBuf st_vert[3], st_tri64[3], st_code[3], st_fsize[3], st_fv[3];
+    DevBuf arena;  // per-wave cell arrays of the 16384-vertex pass
     // last build
     bool valid = false;
     int64_t n = 0;
@@ -51,7 +52,7 @@ struct vd_context {
 
 namespace {
 
-constexpr int kTierCap[3] = {64, 256, 1024};
+using vd::kTierCap;
 
 vd_status ensure(DevBuf& b, size_t bytes) {
     if (bytes == 0) bytes = 16;
@@ -93,6 +94,7 @@ vd_status ensure_stage(vd_context* c, int tier, int64_t slots) {
     const size_t cap = (size_t)kTierCap[tier];
     const size_t sl = (size_t)(slots > 0 ? slots : 1);
     VD_TRY(ensure(c->st_vert[tier], sl * cap * sizeof(float4)));
+    if (cap > 1024) VD_TRY(ensure(c->st_tri64[tier], sl * cap * sizeof(uint64_t)));
     VD_TRY(ensure(c->st_code[tier], sl * cap * sizeof(int32_t)));
     VD_TRY(ensure(c->st_fsize[tier], sl * cap * sizeof(uint16_t)));
     VD_TRY(ensure(c->st_fv[tier], sl * 3 * cap * sizeof(uint16_t)));
@@ -110,6 +112,7 @@ vd::Stage stage_of(vd_context* c, int tier) {
     vd::Stage s;
     s.cap = kTierCap[tier];
     s.vert = as<float4>(c->st_vert[tier]);
+    s.tri64 = kTierCap[tier] > 1024 ? as<uint64_t>(c->st_tri64[tier]) : nullptr;
     s.code = as<int32_t>(c->st_code[tier]);
     s.fsize = as<uint16_t>(c->st_fsize[tier]);
     s.fv = as<uint16_t>(c->st_fv[tier]);
@@ -148,12 +151,13 @@ VD_API void vd_destroy(vd_context* c) {
                      &c->child, &c->pint, &c->pleaf, &c->range, &c->counters, &c->nodes, &c->hist, &c->stmp,
                      &c->bbox, &c->bpart, &c->misc, &c->loc, &c->cnt_v, &c->cnt_f, &c->cnt_n, &c->vol, &c->cen,
                      &c->flags, &c->offv, &c->offf, &c->offn, &c->scan_tmp, &c->list1, &c->list2, &c->stats,
-                     &c->ctr};
+                     &c->ctr, &c->arena};
     for (DevBuf* b : all) release(*b);
     if (c->ev_ready)
         for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
     for (int t = 0; t < 3; ++t) {
         release(c->st_vert[t]);
+        release(c->st_tri64[t]);
         release(c->st_code[t]);
         release(c->st_fsize[t]);
         release(c->st_fv[t]);
@@ -213,7 +217,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     VD_TRY(ensure(c->pint, N * sizeof(int)));
     VD_TRY(ensure(c->pleaf, N * sizeof(int)));
     VD_TRY(ensure(c->range, N * sizeof(int2)));
-    VD_TRY(ensure(c->counters, N * sizeof(uint32_t)));
+    VD_TRY(ensure(c->counters, vd::box_table_size(n) * sizeof(vd::NodeChild)));
     VD_TRY(ensure(c->nodes, N * sizeof(vd::Node)));
     VD_TRY(ensure(c->hist, vd::radix_hist_size(n) * sizeof(uint32_t)));
     VD_TRY(ensure(c->stmp, vd::scan_tmp_size((int64_t)vd::radix_hist_size(n)) * sizeof(uint64_t)));
@@ -264,12 +268,10 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     VD_HIP(vd::launch_losers(spts, skeys, order, n, as<uint8_t>(c->mark), s));
     uint32_t root;
     if (n > o.leaf_size) {
-        VD_HIP(hipMemsetAsync(c->counters.p, 0, N * sizeof(uint32_t), s));
         VD_HIP(vd::launch_karras(skeys, n, as<int2>(c->child), as<int>(c->pint), as<int>(c->pleaf),
                                  as<int2>(c->range), s));
-        VD_HIP(vd::launch_bounds(spts, n, as<int2>(c->child), as<int>(c->pint), as<int>(c->pleaf),
-                                 as<int2>(c->range), as<uint32_t>(c->counters), as<vd::Node>(c->nodes), o.leaf_size,
-                                 s));
+        VD_HIP(vd::launch_bounds(spts, n, as<int2>(c->child), as<int2>(c->range), as<vd::NodeChild>(c->counters),
+                                 as<vd::Node>(c->nodes), o.leaf_size, s));
         root = 0;
     } else {
         root = vd::leaf_ref(0u, (uint32_t)n);
@@ -306,7 +308,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     a.stage = stage_of(c, 0);
     c->tier_slots[0] = (int)n;
     if (prof) VD_HIP(hipEventRecord(c->ev[1], s));
-    VD_HIP(vd::launch_clip(a, vd::clip_grid_waves(0, c->num_cu), s));
+    VD_HIP(vd::launch_clip(a, vd::clip_grid_waves(0, c->num_cu), nullptr, s));
     if (prof) VD_HIP(hipEventRecord(c->ev[2], s));
     uint32_t hmisc[16];
     VD_HIP(hipMemcpyAsync(hmisc, misc, sizeof(hmisc), hipMemcpyDeviceToHost, s));
@@ -330,7 +332,12 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
         if (a.ctr) a.ctr = as<unsigned long long>(c->ctr) + tier * vd::kCtrCount;
         int waves = vd::clip_grid_waves(tier, c->num_cu);
         if ((int64_t)waves > (int64_t)cnt) waves = (int)cnt;
-        VD_HIP(vd::launch_clip(a, waves, s));
+        void* arena = nullptr;
+        if (tier == 2) {
+            VD_TRY(ensure(c->arena, (size_t)waves * vd::arena_bytes_per_wave()));
+            arena = c->arena.p;
+        }
+        VD_HIP(vd::launch_clip(a, waves, arena, s));
         if (prof && tier == 1) VD_HIP(hipEventRecord(c->ev[6], s));
         VD_HIP(hipMemcpyAsync(hmisc, misc, sizeof(hmisc), hipMemcpyDeviceToHost, s));
         VD_HIP(hipStreamSynchronize(s));
@@ -373,7 +380,8 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     *sizes = z;
     if (z.n_failed > 0)
         return fail(VD_ERR_CAPACITY, "vd_build: " + std::to_string(z.n_failed) +
-                                         " cells exceeded the largest capacity (1024 vertices); they are flagged");
+                                         " cells exceeded the largest capacity (" +
+                                         std::to_string(kTierCap[2]) + " vertices); they are flagged");
     return VD_OK;
 }
 

@@ -14,20 +14,26 @@
 // re-tested against the shrunken cell (Alg. 1).
 //
 // How it maps to CDNA4: one 64-wide wavefront owns one cell.  Vertex v lives
-// in lane v % 64 (VPL vertices per lane), in registers: its position, the
-// three planes meeting there, ordered so that their outward normals have a
-// positive determinant, and the three vertices across its edges (edge k is
-// the one that leaves plane k).  Planes live in LDS.  Classifying all
-// vertices against a plane is one ballot; the hole left by removed vertices
-// is closed by one new vertex per crossing edge (supplementary Sec. B): a
-// kept vertex with a removed neighbour across edge k = (planes p_k+1, p_k+2)
-// spawns the vertex (h, p_k+2, p_k+1), and new vertices find each other
-// through two LDS tables keyed by their old planes.  The node queue is spread
-// one entry per lane (min-pop is a wave reduction), node children are tested
-// by two lanes at once, and a leaf's sites are tested by one lane each.
-// Cells that outgrow a tier's capacity are handed to the next tier (256 and
-// 1024 vertices).  The paper's own kernel keeps one cell per thread in
-// global memory; that layout was made for its GPUs and is not used here.
+// in lane v % 64, slot v / 64: its position, the three planes meeting there,
+// ordered so that their outward normals have a positive determinant, and the
+// three vertices across its edges (edge k is the one that leaves plane k).
+// Classifying all vertices against a plane is one ballot per slot; the hole
+// left by removed vertices is closed by one new vertex per crossing edge
+// (supplementary Sec. B): a kept vertex with a removed neighbour across edge
+// k = (planes p_k+1, p_k+2) spawns the vertex (h, p_k+2, p_k+1), and new
+// vertices find each other through two tables keyed by their old planes.  The
+// node queue is spread one entry per lane (min-pop is a wave reduction), node
+// children are tested by two lanes at once, and a leaf's sites by one lane
+// each.
+//
+// Capacity tiers: 64 vertices (one slot; vertex state in registers, planes
+// and tables in LDS), 256 (four slots, same layout) and 16384 (256 slots; all
+// per-cell arrays in a per-wave global arena, slot loops bounded by the slots
+// in use).  A cell that outgrows a tier is handed to the next.  The paper's
+// own kernel keeps one cell per thread in global memory; that layout was made
+// for its GPUs and is not used.
+#include <type_traits>
+
 #include "vd_internal.h"
 
 namespace vd {
@@ -51,6 +57,7 @@ __device__ __forceinline__ float rdl(float v, int l) {
 __device__ __forceinline__ uint32_t rdl(uint32_t v, int l) { return (uint32_t)__builtin_amdgcn_readlane((int)v, l); }
 __device__ __forceinline__ int rdl(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 __device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
+__device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
 __device__ __forceinline__ float wmin(float v) {
     for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
     return uni(v);
@@ -59,57 +66,120 @@ __device__ __forceinline__ float wmax(float v) {
     for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
     return uni(v);
 }
-__device__ __forceinline__ float wsum(float v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return uni(v);
-}
 __device__ __forceinline__ double wsum64(double v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     return v;
 }
 __device__ __forceinline__ uint32_t wsum_u(uint32_t v) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
-}
-// Orders this wave's LDS accesses: all writes before the fence are visible to
-// all lanes' reads after it (one wave, so no workgroup barrier is needed).
-__device__ __forceinline__ void wave_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    return uni(v);
 }
 
-__device__ __forceinline__ uint32_t f10(uint32_t w, int k) { return (w >> (10 * k)) & 1023u; }
-__device__ __forceinline__ uint32_t set10(uint32_t w, int k, uint32_t v) {
-    return (w & ~(1023u << (10 * k))) | (v << (10 * k));
+// Sizes and index packings of a tier.  Three vertex or plane indices are
+// packed into one word: 10 bits each in 32-bit words for the register tiers,
+// 15 bits each in 64-bit words for the arena tier.
+template <int VPL>
+struct Tier {
+    static constexpr int CAP = 64 * VPL;
+    static constexpr bool kReg = VPL <= 16;  // vertex state in registers, slot loops unrolled
+    static constexpr int kB = kReg ? 10 : 15;
+    using W = typename std::conditional<kReg, uint32_t, uint64_t>::type;
+    static constexpr W kMask = (W(1) << kB) - 1;
+    // new-vertex table entries: serial tag above the vertex index
+    static constexpr int kTagShift = kReg ? 12 : 16;
+    static constexpr uint32_t kTagMax = (1u << (32 - kTagShift)) - 2u;
+    __device__ __forceinline__ static uint32_t fld(W w, int k) { return (uint32_t)((w >> (kB * k)) & kMask); }
+    __device__ __forceinline__ static W setfld(W w, int k, uint32_t v) {
+        return (w & ~(kMask << (kB * k))) | (W(v) << (kB * k));
+    }
+    __device__ __forceinline__ static W pack3(uint32_t a, uint32_t b, uint32_t c) {
+        return W(a) | (W(b) << kB) | (W(c) << (2 * kB));
+    }
+};
+
+// Orders this wave's accesses to its per-cell arrays, so that what one lane
+// wrote before is seen by every lane after: LDS for the register tiers (one
+// wave, no workgroup barrier needed), global memory for the arena tier (one
+// wave per workgroup).
+template <bool kLds>
+__device__ __forceinline__ void wave_sync() {
+    if constexpr (kLds) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    }
 }
+
+// Per-slot values of one lane: a register array in the register tiers, a
+// column of an arena array otherwise (element s at m[s * kStride]; stride 64
+// for per-lane values, 1 for wave-uniform ones).
+template <typename X, int N, bool kReg, int kStride>
+struct Col {
+    X r[kReg ? N : 1];
+    X* m = nullptr;
+    __device__ __forceinline__ X& operator[](int s) {
+        if constexpr (kReg) return r[s];
+        else return m[s * kStride];
+    }
+};
+
+// Arena-tier state that the register tiers keep in registers (index
+// slot * 64 + lane for per-lane values, slot for wave-uniform masks).
+template <int VPL, bool kArena = !Tier<VPL>::kReg>
+struct ArenaState {};
+template <int VPL>
+struct ArenaState<VPL, true> {
+    using W = typename Tier<VPL>::W;
+    static constexpr int CAP = Tier<VPL>::CAP;
+    float y0[CAP], y1[CAP], y2[CAP], ev[CAP];  // vertex positions and error scales
+    W vt[CAP], va[CAP];                         // vertex planes and neighbours
+    uint32_t qe[CAP];                           // node queue
+    float qk[CAP];
+    uint32_t cross[CAP], pre[CAP], frank[CAP], nb1[CAP], nb2[CAP];  // clip temporaries
+    W rec[CAP];
+    uint8_t isnew[CAP], amb[CAP];
+    uint64_t alive[VPL], R[VPL], fr[VPL];  // per-slot masks
+};
 
 template <int VPL>
-struct WaveMem {
-    static constexpr int CAP = 64 * VPL;
+struct WaveMem : ArenaState<VPL> {
+    using W = typename Tier<VPL>::W;
+    static constexpr int CAP = Tier<VPL>::CAP;
     float4 pl[CAP];        // planes: a.xyz, b (frame of the site)
     float psb[CAP];        // size of the terms b is formed from (error scale)
     float4 psite[CAP];     // the plane's site (x, y, z, w) for exact re-evaluation
     int32_t pcode[CAP];    // Morton index of the plane's site, or box code -1..-6
     uint32_t ta[CAP];      // clip: new vertex by first old plane | finalize: plane rank
     uint32_t tb[CAP];      // clip: new vertex by second old plane | finalize: facet size
-    uint32_t edge[CAP];    // clip: crossing edges by rank | finalize: facet anchor
     uint32_t sor[CAP];     // clip: free slot of rank | finalize: vertex renumbering
-    uint32_t vtri[CAP];    // finalize: planes of each vertex
-    uint32_t vadj[CAP];    // finalize: neighbours of each vertex
+    uint32_t anchor[CAP];  // finalize: lowest vertex of each facet
+    W edge[CAP];           // clip: crossing edges by rank
+    W vtri[CAP];           // finalize: planes of each vertex
+    W vadj[CAP];           // finalize: neighbours of each vertex
     double vpx[CAP], vpy[CAP], vpz[CAP];  // finalize: FP64 positions relative to vertex 0
     int32_t key[CAP];      // finalize and gc: output codes, used flags
     uint8_t outf[CAP];     // outside flags by vertex index (VPL > 1)
 };
 
-// Error-free-ish helpers for the FP64 re-evaluation of a doubtful side test.
+// A plane in FP64, recomputed from the input coordinates.
 struct P64 {
     double a0, a1, a2, b;
 };
 
 template <int VPL>
 struct Cell {
-    static constexpr int CAP = 64 * VPL;
+    using T = Tier<VPL>;
+    using W = typename T::W;
+    static constexpr int CAP = T::CAP;
+    static constexpr bool kReg = T::kReg;
+    template <typename X>
+    using Lane = Col<X, VPL, kReg, 64>;  // one value per slot of this lane
+    template <typename X>
+    using Wave = Col<X, VPL, kReg, 1>;   // one wave-uniform value per slot
     WaveMem<VPL>& M;
     const ClipArgs& A;
     const uint32_t ln;
@@ -120,29 +190,62 @@ struct Cell {
     uint32_t flags;
     int robust;   // 0: FP32 signs; 1: doubtful signs in FP64; 2: every sign in FP64
     // vertices: slot s of this lane is vertex s*64 + lane
-    float y0[VPL], y1[VPL], y2[VPL], ev[VPL];
-    uint32_t vt[VPL], va[VPL];
-    uint64_t alive[VPL];
+    Lane<float> y0, y1, y2, ev;
+    Lane<W> vt, va;
+    Wave<uint64_t> alive;
     int np;
+    int vhi;  // one past the highest vertex index used since init
     // bounds of the current cell (uniform): AABB in the site's frame, the
     // squared far-corner coordinates, the directional and isotropic radii
     float blo0, blo1, blo2, bhi0, bhi1, bhi2;
     float hx2, hy2, hz2, lx2, ly2, lz2, rmax2, riso2;
-    // queue (one entry per lane and slot)
-    uint32_t qe[VPL];
-    float qk[VPL];
+    // queue (entry q in lane q % 64, slot q / 64)
+    Lane<uint32_t> qe;
+    Lane<float> qk;
     int qn;
     // work counters (uniform), accumulated over all cells of this wave
     uint64_t ctr[kCtrCount];
     bool counting;
 
-    __device__ Cell(WaveMem<VPL>& m, const ClipArgs& a) : M(m), A(a), ln(lane_id()), serial(1) {
+    // the first clip clears the new-vertex tables (the tag counter starts
+    // at its wrap-around value)
+    __device__ Cell(WaveMem<VPL>& m, const ClipArgs& a) : M(m), A(a), ln(lane_id()), serial(T::kTagMax - 1) {
         counting = a.ctr != nullptr;
 #pragma unroll
         for (int c = 0; c < kCtrCount; ++c) ctr[c] = 0;
+        if constexpr (!kReg) {
+            y0.m = M.y0 + ln; y1.m = M.y1 + ln; y2.m = M.y2 + ln; ev.m = M.ev + ln;
+            vt.m = M.vt + ln; va.m = M.va + ln;
+            alive.m = M.alive;
+            qe.m = M.qe + ln; qk.m = M.qk + ln;
+        }
+        vhi = CAP;
     }
     __device__ __forceinline__ void count(int c, uint64_t v) {
         if (counting) ctr[c] += v;
+    }
+    __device__ __forceinline__ void sync() { wave_sync<kReg>(); }
+    // slots that may hold vertices (all of them in the register tiers)
+    __device__ __forceinline__ int nsv() const { return kReg ? VPL : ((vhi + 63) >> 6); }
+    __device__ __forceinline__ uint64_t nalive() {
+        uint64_t c = 0;
+        const int ns = nsv();
+#pragma unroll
+        for (int s = 0; s < (kReg ? VPL : ns); ++s) c += (uint64_t)popc(alive[s]);
+        return c;
+    }
+
+    __device__ __forceinline__ bool is_alive(uint32_t u) {
+        const int sl = (int)(u >> 6);
+        uint64_t al = 0;
+        if constexpr (kReg) {
+#pragma unroll
+            for (int s = 0; s < VPL; ++s)
+                if (s == sl) al = alive[s];
+        } else {
+            if (sl < nsv()) al = alive[sl];
+        }
+        return (al >> (u & 63)) & 1;
     }
 
     // ------------------------------------------------------------ setup
@@ -163,10 +266,15 @@ struct Cell {
             M.pl[ln] = make_float4(a[0], a[1], a[2], b);
             M.psb[ln] = fabsf(b);
             M.pcode[ln] = -(int)(ln + 1);
+            M.psite[ln] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
+        if constexpr (kReg) {
 #pragma unroll
-        for (int s2 = 0; s2 < VPL; ++s2) alive[s2] = 0;
+            for (int s2 = 0; s2 < VPL; ++s2) alive[s2] = 0;
+        }
+        // slots above the first are written by a clip before they are read
         alive[0] = 0xFFull;
+        vhi = 8;
         {
             uint32_t c = ln & 7;
             uint32_t sx = c & 1, sy = (c >> 1) & 1, sz = (c >> 2) & 1;
@@ -174,15 +282,15 @@ struct Cell {
             bool pos = ((sx ^ sy ^ sz) & 1) == 1;  // product of the three normal signs > 0
             uint32_t p1 = pos ? Y : Z, p2 = pos ? Z : Y;
             uint32_t ax1 = p1 >> 1, ax2 = p2 >> 1;
-            vt[0] = X | (p1 << 10) | (p2 << 20);
-            va[0] = (c ^ 1u) | ((c ^ (1u << ax1)) << 10) | ((c ^ (1u << ax2)) << 20);
+            vt[0] = T::pack3(X, p1, p2);
+            va[0] = T::pack3(c ^ 1u, c ^ (1u << ax1), c ^ (1u << ax2));
             y0[0] = sx ? hi[0] : lo[0];
             y1[0] = sy ? hi[1] : lo[1];
             y2[0] = sz ? hi[2] : lo[2];
             ev[0] = fabsf(y0[0]) + fabsf(y1[0]) + fabsf(y2[0]);
         }
         np = 6;
-        wave_sync();
+        sync();
         update_bounds();
         return true;
     }
@@ -190,12 +298,14 @@ struct Cell {
     __device__ void update_bounds() {
         float mn0 = INFINITY, mn1 = INFINITY, mn2 = INFINITY, mx0 = -INFINITY, mx1 = -INFINITY, mx2 = -INFINITY,
               r2 = 0.f;
+        const int ns = nsv();
 #pragma unroll
-        for (int s = 0; s < VPL; ++s) {
+        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
             if ((alive[s] >> ln) & 1) {
-                mn0 = fminf(mn0, y0[s]); mn1 = fminf(mn1, y1[s]); mn2 = fminf(mn2, y2[s]);
-                mx0 = fmaxf(mx0, y0[s]); mx1 = fmaxf(mx1, y1[s]); mx2 = fmaxf(mx2, y2[s]);
-                r2 = fmaxf(r2, fmaf(y0[s], y0[s], fmaf(y1[s], y1[s], y2[s] * y2[s])));
+                const float a = y0[s], b = y1[s], c = y2[s];
+                mn0 = fminf(mn0, a); mn1 = fminf(mn1, b); mn2 = fminf(mn2, c);
+                mx0 = fmaxf(mx0, a); mx1 = fmaxf(mx1, b); mx2 = fmaxf(mx2, c);
+                r2 = fmaxf(r2, fmaf(a, a, fmaf(b, b, c * c)));
             }
         }
         float l0 = wmin(mn0), l1 = wmin(mn1), l2 = wmin(mn2);
@@ -220,21 +330,18 @@ struct Cell {
     // |v - p_j|^2 - w_j < |v|^2 - w_i, and |v - p_j|^2 >= dist(v, box)^2.
     // Returns true if some vertex might be cut (the box cannot be skipped).
     __device__ bool ball_hit(float lx, float ly, float lz, float hx, float hy, float hz, float wm) {
-        if (counting) {
-            uint64_t nal = 0;
-#pragma unroll
-            for (int s = 0; s < VPL; ++s) nal += (uint64_t)popc(alive[s]);
-            count(kCtrBall, nal);
-        }
+        if (counting) count(kCtrBall, nalive());
         bool hit = false;
+        const int ns = nsv();
 #pragma unroll
-        for (int s = 0; s < VPL; ++s) {
+        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
             if ((alive[s] >> ln) & 1) {
-                float dx = fmaxf(fmaxf(lx - y0[s], y0[s] - hx), 0.f);
-                float dy = fmaxf(fmaxf(ly - y1[s], y1[s] - hy), 0.f);
-                float dz = fmaxf(fmaxf(lz - y2[s], y2[s] - hz), 0.f);
+                const float a = y0[s], b = y1[s], c = y2[s];
+                float dx = fmaxf(fmaxf(lx - a, a - hx), 0.f);
+                float dy = fmaxf(fmaxf(ly - b, b - hy), 0.f);
+                float dz = fmaxf(fmaxf(lz - c, c - hz), 0.f);
                 float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                float r2 = fmaf(y0[s], y0[s], fmaf(y1[s], y1[s], y2[s] * y2[s]));
+                float r2 = fmaf(a, a, fmaf(b, b, c * c));
                 float lhs = d2 - wm, rhs = r2 - pw;
                 hit |= lhs - rhs <= 16.f * kU * (d2 + r2 + fabsf(wm) + fabsf(pw));
             }
@@ -242,8 +349,7 @@ struct Cell {
         return ballot(hit) != 0;
     }
 
-    // Broadcasts child record lanes' boxes and applies the ball test to the
-    // child held by lane `l` (its box relative to the site).
+    // Applies the ball test to the child record held by lane `l`.
     __device__ bool ball_hit_lane(const NodeChild& c, int l) {
         float lx = rdl(c.lo[0] - px, l), ly = rdl(c.lo[1] - py, l), lz = rdl(c.lo[2] - pz, l);
         float hx = rdl(c.hi[0] - px, l), hy = rdl(c.hi[1] - py, l), hz = rdl(c.hi[2] - pz, l);
@@ -252,7 +358,7 @@ struct Cell {
     }
 
     // ------------------------------------------------------------ FP64 side test
-    // Plane q (LDS) in FP64, recomputed from the input coordinates: a = p_j - p_i
+    // Plane q in FP64, recomputed from the input coordinates: a = p_j - p_i
     // is exact in FP64, b = (|a|^2 + w_i - w_j) / 2 nearly so.
     __device__ P64 plane64(uint32_t q) const { return plane64(M.pcode[q], M.psite[q]); }
 
@@ -287,11 +393,11 @@ struct Cell {
         n[2] = A0.b * bc2 + B0.b * ca2 + C0.b * ab2;
     }
 
-    // Side of vertex (planes t) w.r.t. plane h, recomputed in FP64 from the
-    // input coordinates.  Returns +1 outside, -1 inside, 0 undecided.
-    __device__ int side64(uint32_t t, const P64& h) const {
+    // Side of the vertex with planes t w.r.t. plane h, recomputed in FP64 from
+    // the input coordinates.  Returns +1 outside, -1 inside, 0 undecided.
+    __device__ int side64(W t, const P64& h) const {
         double n[3], det;
-        cramer64(plane64(f10(t, 0)), plane64(f10(t, 1)), plane64(f10(t, 2)), n, &det);
+        cramer64(plane64(T::fld(t, 0)), plane64(T::fld(t, 1)), plane64(T::fld(t, 2)), n, &det);
         // s * det = a_h . n - b_h det, evaluated without dividing
         double s = h.a0 * n[0] + h.a1 * n[1] + h.a2 * n[2] - h.b * det;
         if (det < 0) s = -s;
@@ -305,35 +411,33 @@ struct Cell {
     // mode 0: plain FP32 signs; 1: doubtful signs re-evaluated in FP64;
     // 2: doubtful signs taken as inside; 3: every sign evaluated in FP64.
     __device__ void classify(float ax, float ay, float az, float b, float sbh, int32_t hcode, float4 hsite,
-                             int mode, uint64_t* R) {
+                             int mode, Wave<uint64_t>& R) {
         const float an1 = fabsf(ax) + fabsf(ay) + fabsf(az);
-        if (counting && mode != 2) {
-            uint64_t nal = 0;
-#pragma unroll
-            for (int s = 0; s < VPL; ++s) nal += (uint64_t)popc(alive[s]);
-            count(kCtrClassify, nal);
-        }
+        if (counting && mode != 2) count(kCtrClassify, nalive());
+        const int ns = nsv();
         uint64_t amb_any = 0;
-        bool amb[VPL];
+        Lane<uint8_t> amb;
+        if constexpr (!kReg) amb.m = M.amb + ln;
 #pragma unroll
-        for (int s = 0; s < VPL; ++s) {
-            float sv = fmaf(ax, y0[s], fmaf(ay, y1[s], fmaf(az, y2[s], -b)));
-            bool al = (alive[s] >> ln) & 1;
+        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
+            const float sv = fmaf(ax, y0[s], fmaf(ay, y1[s], fmaf(az, y2[s], -b)));
+            const bool al = (alive[s] >> ln) & 1;
             bool o = al && sv > 0.f;
-            amb[s] = false;
+            bool am = false;
             if (mode != 0) {
                 float beta = 64.f * kU * (an1 * ev[s] + sbh);
-                amb[s] = al && (mode == 3 || fabsf(sv) <= beta);
-                if (amb[s] && mode == 2) o = false;
+                am = al && (mode == 3 || fabsf(sv) <= beta);
+                if (am && mode == 2) o = false;
             }
+            amb[s] = am;
             R[s] = ballot(o);
-            amb_any |= ballot(amb[s]);
+            amb_any |= ballot(am);
         }
         if ((mode == 1 || mode == 3) && amb_any) {
             flags |= kFlagFP64;
             P64 h = plane64(hcode, hsite);
 #pragma unroll
-            for (int s = 0; s < VPL; ++s) {
+            for (int s = 0; s < (kReg ? VPL : ns); ++s) {
                 bool o = (R[s] >> ln) & 1;
                 bool unsure = false;
                 if (amb[s]) {
@@ -348,13 +452,14 @@ struct Cell {
     }
 
     // Tries the clip with the given outside masks; on an inconsistent
-    // boundary returns false and leaves the cell untouched.
-    __device__ int apply(const uint64_t* R, float ax, float ay, float az, float b, float sbh, int32_t hcode,
+    // boundary sets *consistent = false and leaves the cell untouched.
+    __device__ int apply(Wave<uint64_t>& R, float ax, float ay, float az, float b, float sbh, int32_t hcode,
                          float4 hsite, bool* consistent) {
         *consistent = true;
+        const int ns = nsv();
         bool any = false, all = true;
 #pragma unroll
-        for (int s = 0; s < VPL; ++s) {
+        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
             any |= R[s] != 0;
             all &= R[s] == alive[s];
         }
@@ -366,24 +471,33 @@ struct Cell {
         }
         if constexpr (VPL > 1) {
 #pragma unroll
-            for (int s = 0; s < VPL; ++s) M.outf[s * 64 + ln] = (uint8_t)((R[s] >> ln) & 1);
-            wave_sync();
+            for (int s = 0; s < (kReg ? VPL : ns); ++s) M.outf[s * 64 + ln] = (uint8_t)((R[s] >> ln) & 1);
+            sync();
         }
         auto is_out = [&](uint32_t v) -> bool {
             if constexpr (VPL == 1) return (R[0] >> v) & 1;
             else return M.outf[v] != 0;
         };
+        Lane<uint32_t> cross, pre, frank, nb1, nb2;
+        Lane<W> rec;
+        Lane<uint8_t> isnew;
+        Wave<uint64_t> fr;
+        if constexpr (!kReg) {
+            cross.m = M.cross + ln; pre.m = M.pre + ln; frank.m = M.frank + ln;
+            nb1.m = M.nb1 + ln; nb2.m = M.nb2 + ln; rec.m = M.rec + ln; isnew.m = M.isnew + ln;
+            fr.m = M.fr;
+        }
         // crossing edges of kept vertices, ranked over the wave
-        uint32_t cross[VPL], pre[VPL];
         uint32_t m = 0;
 #pragma unroll
-        for (int s = 0; s < VPL; ++s) {
+        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
             bool kept = ((alive[s] & ~R[s]) >> ln) & 1;
             uint32_t c = 0, cnt = 0;
             if (kept) {
+                const W nbr = va[s];
 #pragma unroll
                 for (int e = 0; e < 3; ++e)
-                    if (is_out(f10(va[s], e))) {
+                    if (is_out(T::fld(nbr, e))) {
                         c |= 1u << e;
                         ++cnt;
                     }
@@ -393,79 +507,94 @@ struct Cell {
             pre[s] = m + mbcnt(b0) + 2 * mbcnt(b1);
             m += popc(b0) + 2 * popc(b1);
         }
-        // free slots (dead or removed), ranked
-        uint32_t nfree = 0, frank[VPL];
-        uint64_t fr[VPL];
+        // free slots (dead or removed), ranked; slots above the used ones are free
+        const int nsf = kReg ? VPL : min(VPL, ns + (int)((m + 63) >> 6) + 1);
+        uint32_t nfree = 0;
 #pragma unroll
-        for (int s = 0; s < VPL; ++s) {
-            fr[s] = ~alive[s] | R[s];
-            frank[s] = nfree + mbcnt(fr[s]);
-            nfree += popc(fr[s]);
+        for (int s = 0; s < (kReg ? VPL : nsf); ++s) {
+            const uint64_t f = (s < ns) ? (~alive[s] | R[s]) : ~0ull;
+            fr[s] = f;
+            frank[s] = nfree + mbcnt(f);
+            nfree += popc(f);
+        }
+        if (m == 0) {  // some vertex is cut off but no edge crosses the plane
+            *consistent = false;
+            return kNone;
         }
         if (m > nfree) return kOverflow;
         const uint32_t h = (uint32_t)np;
         ++serial;
-        if (serial >= 0xFFFFEu) {  // tag space exhausted: clear the tables
+        if (serial >= T::kTagMax) {  // tag space exhausted: clear the tables
             for (int q = ln; q < CAP; q += 64) { M.ta[q] = 0; M.tb[q] = 0; }
             serial = 1;
         }
-        const uint32_t tag = serial << 12;
+        const uint32_t tag = serial << T::kTagShift;
+        const uint32_t vmask = (1u << T::kTagShift) - 1u;
 #pragma unroll
-        for (int s = 0; s < VPL; ++s)
-            if (((fr[s] >> ln) & 1) && frank[s] < m) M.sor[frank[s]] = s * 64 + ln;
+        for (int s = 0; s < (kReg ? VPL : nsf); ++s) {
+            const bool nw = ((fr[s] >> ln) & 1) && frank[s] < m;
+            isnew[s] = nw;
+            if (nw) M.sor[frank[s]] = s * 64 + ln;
+        }
 #pragma unroll
-        for (int s = 0; s < VPL; ++s) {
-            if (cross[s]) {
+        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
+            const uint32_t c = cross[s];
+            if (c) {
                 uint32_t j = pre[s];
+                const W t = vt[s];
 #pragma unroll
                 for (int e = 0; e < 3; ++e)
-                    if ((cross[s] >> e) & 1) {
-                        uint32_t x = f10(vt[s], (e + 2) % 3), y = f10(vt[s], (e + 1) % 3);
-                        M.edge[j++] = (uint32_t)(s * 64 + ln) | (x << 10) | (y << 20);
+                    if ((c >> e) & 1) {
+                        uint32_t x = T::fld(t, (e + 2) % 3), y = T::fld(t, (e + 1) % 3);
+                        M.edge[j++] = T::pack3((uint32_t)(s * 64 + ln), x, y);
                     }
             }
         }
-        wave_sync();
-        bool isnew[VPL];
-        uint32_t rec[VPL];
+        sync();
 #pragma unroll
-        for (int s = 0; s < VPL; ++s) {
-            isnew[s] = ((fr[s] >> ln) & 1) && frank[s] < m;
-            rec[s] = 0;
+        for (int s = 0; s < (kReg ? VPL : nsf); ++s) {
+            W r = 0;
             if (isnew[s]) {
-                rec[s] = M.edge[frank[s]];
+                r = M.edge[frank[s]];
                 uint32_t me = tag | (uint32_t)(s * 64 + ln);
-                M.ta[f10(rec[s], 1)] = me;
-                M.tb[f10(rec[s], 2)] = me;
+                M.ta[T::fld(r, 1)] = me;
+                M.tb[T::fld(r, 2)] = me;
             }
+            rec[s] = r;
         }
-        wave_sync();
+        sync();
         bool bad = false;
-        uint32_t nb1[VPL], nb2[VPL];
 #pragma unroll
-        for (int s = 0; s < VPL; ++s) {
-            nb1[s] = nb2[s] = 0;
+        for (int s = 0; s < (kReg ? VPL : nsf); ++s) {
+            uint32_t n1 = 0, n2 = 0;
             if (isnew[s]) {
+                const W r = rec[s];
                 uint32_t me = tag | (uint32_t)(s * 64 + ln);
-                uint32_t x = f10(rec[s], 1), y = f10(rec[s], 2);
+                uint32_t x = T::fld(r, 1), y = T::fld(r, 2);
                 uint32_t a1 = M.ta[y], a2 = M.tb[x];
                 bad |= M.ta[x] != me || M.tb[y] != me;
-                bad |= (a1 & ~4095u) != tag || (a2 & ~4095u) != tag;
-                nb1[s] = a1 & 4095u;
-                nb2[s] = a2 & 4095u;
+                bad |= (a1 & ~vmask) != tag || (a2 & ~vmask) != tag;
+                n1 = a1 & vmask;
+                n2 = a2 & vmask;
             }
+            nb1[s] = n1;
+            nb2[s] = n2;
         }
         if (!ballot(bad)) {
             // the new vertices must form one cycle around the new facet:
             // following "next around h" from the first one returns after m steps
-            const uint32_t start = (uint32_t)__builtin_amdgcn_readfirstlane((int)M.sor[0]);
+            const uint32_t start = uni(M.sor[0]);
             uint32_t v = start, steps = 0;
             do {
-                const uint32_t sl = v >> 6, lv = v & 63;
+                const int sl = (int)(v >> 6), lv = (int)(v & 63);
                 uint32_t nxt = 0xFFFFFFFFu;
+                if constexpr (kReg) {
 #pragma unroll
-                for (int s = 0; s < VPL; ++s)
-                    if ((uint32_t)s == sl) nxt = rdl(nb1[s], (int)lv);
+                    for (int s = 0; s < VPL; ++s)
+                        if (s == sl) nxt = rdl(nb1[s], lv);
+                } else {
+                    if (sl < nsf) nxt = rdl(nb1[sl], lv);
+                }
                 v = nxt;
                 ++steps;
             } while (v != start && steps <= m);
@@ -477,21 +606,25 @@ struct Cell {
         }
         // commit: kept vertices point at their new neighbours
 #pragma unroll
-        for (int s = 0; s < VPL; ++s) {
-            if (cross[s]) {
+        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
+            const uint32_t c = cross[s];
+            if (c) {
                 uint32_t j = pre[s];
+                W a = va[s];
 #pragma unroll
                 for (int e = 0; e < 3; ++e)
-                    if ((cross[s] >> e) & 1) va[s] = set10(va[s], e, M.sor[j++]);
+                    if ((c >> e) & 1) a = T::setfld(a, e, M.sor[j++]);
+                va[s] = a;
             }
         }
         // new vertices: planes (h, x, y), position by Cramer's rule
 #pragma unroll
-        for (int s = 0; s < VPL; ++s) {
+        for (int s = 0; s < (kReg ? VPL : nsf); ++s) {
             if (isnew[s]) {
-                uint32_t x = f10(rec[s], 1), y = f10(rec[s], 2);
-                vt[s] = h | (x << 10) | (y << 20);
-                va[s] = f10(rec[s], 0) | (nb1[s] << 10) | (nb2[s] << 20);
+                const W r = rec[s];
+                uint32_t x = T::fld(r, 1), y = T::fld(r, 2);
+                vt[s] = T::pack3(h, x, y);
+                va[s] = T::pack3(T::fld(r, 0), nb1[s], nb2[s]);
                 float4 P = M.pl[x], Q = M.pl[y];
                 float sbx = M.psb[x], sby = M.psb[y];
                 // n0 = a_x cross a_y, n1 = a_y cross a_h, n2 = a_h cross a_x
@@ -500,16 +633,27 @@ struct Cell {
                 float n20 = ay * P.z - az * P.y, n21 = az * P.x - ax * P.z, n22 = ax * P.y - ay * P.x;
                 float det = fmaf(ax, n00, fmaf(ay, n01, az * n02));
                 float inv = 1.0f / det;
-                y0[s] = (b * n00 + P.w * n10 + Q.w * n20) * inv;
-                y1[s] = (b * n01 + P.w * n11 + Q.w * n21) * inv;
-                y2[s] = (b * n02 + P.w * n12 + Q.w * n22) * inv;
+                const float q0 = (b * n00 + P.w * n10 + Q.w * n20) * inv;
+                const float q1 = (b * n01 + P.w * n11 + Q.w * n21) * inv;
+                const float q2 = (b * n02 + P.w * n12 + Q.w * n22) * inv;
+                y0[s] = q0;
+                y1[s] = q1;
+                y2[s] = q2;
                 float e = (sbh * (fabsf(n00) + fabsf(n01) + fabsf(n02)) + sbx * (fabsf(n10) + fabsf(n11) + fabsf(n12)) +
                            sby * (fabsf(n20) + fabsf(n21) + fabsf(n22))) * fabsf(inv);
-                ev[s] = e + fabsf(y0[s]) + fabsf(y1[s]) + fabsf(y2[s]);
+                ev[s] = e + fabsf(q0) + fabsf(q1) + fabsf(q2);
             }
         }
 #pragma unroll
-        for (int s = 0; s < VPL; ++s) alive[s] = (alive[s] & ~R[s]) | ballot(isnew[s]);
+        for (int s = 0; s < (kReg ? VPL : nsf); ++s) {
+            const uint64_t keep = (s < ns) ? (alive[s] & ~R[s]) : 0ull;
+            alive[s] = keep | ballot(isnew[s] != 0);
+        }
+        if constexpr (!kReg) {
+            // free slots are taken in increasing order: the last rank's is the highest
+            const int top = (int)uni(M.sor[m - 1]) + 1;
+            if (top > vhi) vhi = top;
+        }
         if (ln == 0) {
             M.pl[h] = make_float4(ax, ay, az, b);
             M.psb[h] = sbh;
@@ -517,18 +661,19 @@ struct Cell {
             M.psite[h] = hsite;
         }
         np = (int)h + 1;
-        wave_sync();
+        sync();
         count(kCtrNewVertex, m);
         count(kCtrEffective, 1);
         return kChanged;
     }
 
     // Plain FP32 signs unless the cell is being rebuilt robustly; an
-    // inconsistent boundary in FP32 asks for that rebuild, in the robust mode
+    // inconsistent boundary in FP32 asks for that rebuild; in the robust modes
     // doubtful signs fall back to "inside" and, failing that, the plane is
     // skipped and the cell flagged.
     __device__ int clip(float ax, float ay, float az, float b, float sbh, int32_t hcode, float4 hsite) {
-        uint64_t R[VPL];
+        Wave<uint64_t> R;
+        if constexpr (!kReg) R.m = M.R;
         count(kCtrClip, 1);
         classify(ax, ay, az, b, sbh, hcode, hsite, robust == 0 ? 0 : (robust == 1 ? 1 : 3), R);
         bool ok;
@@ -543,60 +688,95 @@ struct Cell {
 
     // Drop planes no vertex uses (supplementary Sec. A, "Garbage collection").
     __device__ void gc() {
-        for (int q = ln; q < CAP; q += 64) M.key[q] = 0;
-        wave_sync();
+        const int ns = nsv();
+        for (int q = ln; q < np; q += 64) M.key[q] = 0;
+        sync();
 #pragma unroll
-        for (int s = 0; s < VPL; ++s)
+        for (int s = 0; s < (kReg ? VPL : ns); ++s)
             if ((alive[s] >> ln) & 1) {
-                M.key[f10(vt[s], 0)] = 1;
-                M.key[f10(vt[s], 1)] = 1;
-                M.key[f10(vt[s], 2)] = 1;
+                const W t = vt[s];
+                M.key[T::fld(t, 0)] = 1;
+                M.key[T::fld(t, 1)] = 1;
+                M.key[T::fld(t, 2)] = 1;
             }
-        wave_sync();
-        float4 pl[VPL], ps[VPL];
-        float sb[VPL];
-        int32_t pc[VPL];
-        uint32_t dst[VPL];
-        bool used[VPL];
+        sync();
         uint32_t cnt = 0;
+        if constexpr (kReg) {
+            float4 pl[VPL], ps[VPL];
+            float sb[VPL];
+            int32_t pc[VPL];
+            uint32_t dst[VPL];
+            bool used[VPL];
 #pragma unroll
-        for (int s = 0; s < VPL; ++s) {
-            int q = s * 64 + ln;
-            used[s] = q < np && M.key[q] != 0;
-            uint64_t u = ballot(used[s]);
-            dst[s] = cnt + mbcnt(u);
-            cnt += popc(u);
-            if (used[s]) {
-                pl[s] = M.pl[q];
-                ps[s] = M.psite[q];
-                sb[s] = M.psb[q];
-                pc[s] = M.pcode[q];
+            for (int s = 0; s < VPL; ++s) {
+                int q = s * 64 + ln;
+                used[s] = q < np && M.key[q] != 0;
+                uint64_t u = ballot(used[s]);
+                dst[s] = cnt + mbcnt(u);
+                cnt += popc(u);
+                if (used[s]) {
+                    pl[s] = M.pl[q];
+                    ps[s] = M.psite[q];
+                    sb[s] = M.psb[q];
+                    pc[s] = M.pcode[q];
+                }
+            }
+            sync();
+#pragma unroll
+            for (int s = 0; s < VPL; ++s) {
+                int q = s * 64 + ln;
+                if (used[s]) {
+                    M.pl[dst[s]] = pl[s];
+                    M.psite[dst[s]] = ps[s];
+                    M.psb[dst[s]] = sb[s];
+                    M.pcode[dst[s]] = pc[s];
+                    M.key[q] = (int32_t)dst[s];
+                }
+            }
+        } else {
+            // in place, 64 planes at a time: a destination never lies above
+            // its source, and every source of a chunk is read before any of
+            // its destinations is written
+            for (int q0 = 0; q0 < np; q0 += 64) {
+                const int q = q0 + (int)ln;
+                const bool used = q < np && M.key[q] != 0;
+                const uint64_t u = ballot(used);
+                const uint32_t dst = cnt + mbcnt(u);
+                cnt += popc(u);
+                float4 pl = make_float4(0.f, 0.f, 0.f, 0.f), ps = pl;
+                float sb = 0.f;
+                int32_t pc = 0;
+                if (used) {
+                    pl = M.pl[q];
+                    ps = M.psite[q];
+                    sb = M.psb[q];
+                    pc = M.pcode[q];
+                }
+                sync();
+                if (used) {
+                    M.pl[dst] = pl;
+                    M.psite[dst] = ps;
+                    M.psb[dst] = sb;
+                    M.pcode[dst] = pc;
+                    M.key[q] = (int32_t)dst;
+                }
+                sync();
             }
         }
-        wave_sync();
+        sync();
 #pragma unroll
-        for (int s = 0; s < VPL; ++s) {
-            int q = s * 64 + ln;
-            if (used[s]) {
-                M.pl[dst[s]] = pl[s];
-                M.psite[dst[s]] = ps[s];
-                M.psb[dst[s]] = sb[s];
-                M.pcode[dst[s]] = pc[s];
-                M.key[q] = (int32_t)dst[s];
+        for (int s = 0; s < (kReg ? VPL : ns); ++s)
+            if ((alive[s] >> ln) & 1) {
+                const W t = vt[s];
+                vt[s] = T::pack3((uint32_t)M.key[T::fld(t, 0)], (uint32_t)M.key[T::fld(t, 1)],
+                                 (uint32_t)M.key[T::fld(t, 2)]);
             }
-        }
-        wave_sync();
-#pragma unroll
-        for (int s = 0; s < VPL; ++s)
-            if ((alive[s] >> ln) & 1)
-                vt[s] = (uint32_t)M.key[f10(vt[s], 0)] | ((uint32_t)M.key[f10(vt[s], 1)] << 10) |
-                        ((uint32_t)M.key[f10(vt[s], 2)] << 20);
         np = (int)cnt;
-        wave_sync();
+        sync();
     }
 
     // ------------------------------------------------------------ traversal
-    // Tests child `s` of internal node `node` against the current cell.
+    // Tests one child record against the current cell (Sec. 4.2.2).
     __device__ void node_test(const NodeChild& c, float* key, bool* cull, float* delta) const {
         float blx = c.lo[0] - px, bly = c.lo[1] - py, blz = c.lo[2] - pz;
         float bhx = c.hi[0] - px, bhy = c.hi[1] - py, bhz = c.hi[2] - pz;
@@ -633,18 +813,26 @@ struct Cell {
 
     __device__ void push(uint32_t e, float k) {
         const int slot = qn >> 6, l = qn & 63;
+        if constexpr (kReg) {
 #pragma unroll
-        for (int s = 0; s < VPL; ++s)
-            if (s == slot && (int)ln == l) {
-                qe[s] = e;
-                qk[s] = k;
+            for (int s = 0; s < VPL; ++s)
+                if (s == slot && (int)ln == l) {
+                    qe[s] = e;
+                    qk[s] = k;
+                }
+        } else {
+            if ((int)ln == l) {
+                qe[slot] = e;
+                qk[slot] = k;
             }
+        }
         ++qn;
     }
 
     // Removes and returns the entry with the smallest key (best-first), or
     // the last pushed one (depth-first).
     __device__ void pop(uint32_t* e, float* k) {
+        const int nq = (qn + 63) >> 6;
         int S, L;
         if (A.traversal == 2) {
             S = (qn - 1) >> 6;
@@ -653,11 +841,14 @@ struct Cell {
             float bk = INFINITY;
             int bs = 0;
 #pragma unroll
-            for (int s = 0; s < VPL; ++s) {
+            for (int s = 0; s < (kReg ? VPL : nq); ++s) {
                 int idx = s * 64 + (int)ln;
-                if (idx < qn && qk[s] < bk) {
-                    bk = qk[s];
-                    bs = s;
+                if (idx < qn) {
+                    const float kk = qk[s];
+                    if (kk < bk) {
+                        bk = kk;
+                        bs = s;
+                    }
                 }
             }
             float m = wmin(bk);
@@ -665,29 +856,38 @@ struct Cell {
             L = msk ? lowest(msk) : 0;
             S = rdl(bs, L);
         }
-        uint32_t ee = 0;
-        float kk = 0.f;
-#pragma unroll
-        for (int s = 0; s < VPL; ++s)
-            if (s == S) {
-                ee = rdl(qe[s], L);
-                kk = rdl(qk[s], L);
-            }
+        uint32_t ee = 0, le = 0;
+        float kk = 0.f, lk = 0.f;
         const int last = qn - 1, ls = last >> 6, ll = last & 63;
-        uint32_t le = 0;
-        float lk = 0.f;
+        if constexpr (kReg) {
 #pragma unroll
-        for (int s = 0; s < VPL; ++s)
-            if (s == ls) {
-                le = rdl(qe[s], ll);
-                lk = rdl(qk[s], ll);
-            }
+            for (int s = 0; s < VPL; ++s)
+                if (s == S) {
+                    ee = rdl(qe[s], L);
+                    kk = rdl(qk[s], L);
+                }
 #pragma unroll
-        for (int s = 0; s < VPL; ++s)
-            if (s == S && (int)ln == L) {
-                qe[s] = le;
-                qk[s] = lk;
+            for (int s = 0; s < VPL; ++s)
+                if (s == ls) {
+                    le = rdl(qe[s], ll);
+                    lk = rdl(qk[s], ll);
+                }
+#pragma unroll
+            for (int s = 0; s < VPL; ++s)
+                if (s == S && (int)ln == L) {
+                    qe[s] = le;
+                    qk[s] = lk;
+                }
+        } else {
+            ee = rdl(qe[S], L);
+            kk = rdl(qk[S], L);
+            le = rdl(qe[ls], ll);
+            lk = rdl(qk[ls], ll);
+            if ((int)ln == L) {
+                qe[S] = le;
+                qk[S] = lk;
             }
+        }
         --qn;
         *e = ee;
         *k = kk;
@@ -695,13 +895,13 @@ struct Cell {
 
     // Clips by the candidate sites of one leaf; nearest plane first.
     __device__ int leaf(uint32_t ref) {
-        const uint32_t first = leaf_first(ref), count = leaf_count(ref);
-        this->count(kCtrLeaf, 1);
-        this->count(kCtrSite, count);
+        const uint32_t first = leaf_first(ref), nsite = leaf_count(ref);
+        count(kCtrLeaf, 1);
+        count(kCtrSite, nsite);
         float ax = 0.f, ay = 0.f, az = 0.f, a2 = 0.f, b = 0.f, dw = 0.f, key = INFINITY;
         float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
         bool cand = false;
-        if (ln < count) {
+        if (ln < nsite) {
             uint32_t j = first + ln;
             q = A.pts[j];
             if (j != self && q.w != -INFINITY) {
@@ -718,9 +918,9 @@ struct Cell {
             if (A.culling == 3) {
                 // the plane misses the cell's AABB: max over the box of a.y <= b
                 float cx = ax >= 0.f ? bhi0 : blo0, cy = ay >= 0.f ? bhi1 : blo1, cz = az >= 0.f ? bhi2 : blo2;
-                float m = fmaf(ax, cx, fmaf(ay, cy, az * cz));
+                float mm = fmaf(ax, cx, fmaf(ay, cy, az * cz));
                 float slack = 8.f * kU * (fabsf(ax * cx) + fabsf(ay * cy) + fabsf(az * cz) + a2 + fabsf(dw));
-                return m > b - slack;
+                return mm > b - slack;
             }
             float r2 = radius2_toward(ax, ay, az);
             float t = b - 4.f * kU * (2.f * a2 + fabsf(dw) + r2);
@@ -758,7 +958,7 @@ struct Cell {
         c->hi[0] = v.x; c->hi[1] = v.y; c->hi[2] = v.z; c->ref = __float_as_uint(v.w);
     }
 
-    // Alg. 1.  Returns kNone when done, kEmptied or kOverflow.
+    // Alg. 1.  Returns kNone when done, kEmptied, kOverflow or kRestart.
     __device__ int traverse() {
         uint32_t cur = A.root;
         bool have = true;
@@ -773,16 +973,14 @@ struct Cell {
                 float key = 0.f, delta = 0.f;
                 bool cull = true;
                 uint32_t ref = 0;
+                NodeChild cc;
                 if (ln < 2) {
-                    NodeChild c;
-                    load_child(node, (int)ln, &c);
-                    node_test(c, &key, &cull, &delta);
-                    ref = c.ref;
+                    load_child(node, (int)ln, &cc);
+                    node_test(cc, &key, &cull, &delta);
+                    ref = cc.ref;
                 }
                 bool c0 = rdl((int)cull, 0) != 0, c1 = rdl((int)cull, 1) != 0;
                 if (A.culling == 3) {
-                    NodeChild cc;
-                    if (ln < 2) load_child(node, (int)ln, &cc);
                     if (!c0 && !ball_hit_lane(cc, 0)) c0 = true;
                     if (!c1 && !ball_hit_lane(cc, 1)) c1 = true;
                 }
@@ -839,9 +1037,9 @@ struct Cell {
 
     // ------------------------------------------------------------ output
     // FP64 position of a vertex (relative to the site) from its three planes.
-    __device__ void pos64(uint32_t t, float fx, float fy, float fz, double* y) const {
+    __device__ void pos64(W t, float fx, float fy, float fz, double* y) const {
         double n[3], det;
-        cramer64(plane64(f10(t, 0)), plane64(f10(t, 1)), plane64(f10(t, 2)), n, &det);
+        cramer64(plane64(T::fld(t, 0)), plane64(T::fld(t, 1)), plane64(T::fld(t, 2)), n, &det);
         if (det != 0.0) {
             double inv = 1.0 / det;
             y[0] = n[0] * inv; y[1] = n[1] * inv; y[2] = n[2] * inv;
@@ -855,58 +1053,79 @@ struct Cell {
     __device__ bool finalize(uint32_t slot, uint32_t orig) {
         gc();
         const int F = np;
+        const int ns = nsv();
         // facet order: ascending output code (box faces -6..-1, then original site ids)
         for (int q = ln; q < F; q += 64) {
             int32_t c = M.pcode[q];
             M.key[q] = c >= 0 ? (int32_t)A.order[c] : c;
         }
-        wave_sync();
+        sync();
         for (int q = ln; q < F; q += 64) {
             int32_t mine = M.key[q];
             uint32_t r = 0;
             for (int t = 0; t < F; ++t) r += M.key[t] < mine ? 1u : 0u;
             M.ta[q] = r;
             M.tb[q] = 0;
-            M.edge[q] = 0xFFFFFFFFu;
+            M.anchor[q] = 0xFFFFFFFFu;
         }
         const Stage& st = A.stage;
         int32_t* codes = st.code + (int64_t)slot * st.cap;
         for (int q = ln; q < F; q += 64) codes[M.ta[q]] = M.key[q];
         // vertex renumbering 0..nv-1 (slot-major)
-        uint32_t vid[VPL];
         uint32_t nv = 0;
         int s0 = -1;
 #pragma unroll
-        for (int s = 0; s < VPL; ++s) {
-            vid[s] = nv + mbcnt(alive[s]);
-            if (s0 < 0 && alive[s]) s0 = s;
-            nv += popc(alive[s]);
-            if ((alive[s] >> ln) & 1) M.sor[s * 64 + ln] = vid[s];
+        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
+            const uint64_t al = alive[s];
+            if (s0 < 0 && al) s0 = s;
+            if ((al >> ln) & 1) M.sor[s * 64 + ln] = nv + mbcnt(al);
+            nv += popc(al);
         }
-        wave_sync();
+        sync();
         if (s0 < 0) return false;
         // reference point of the tetrahedral fan: vertex 0, in FP64
         double ref[3] = {0.0, 0.0, 0.0};
         {
             const int l0 = lowest(alive[s0]);
             double y[3] = {0.0, 0.0, 0.0};
+            if constexpr (kReg) {
 #pragma unroll
-            for (int s = 0; s < VPL; ++s)
-                if (s == s0 && (int)ln == l0) pos64(vt[s], y0[s], y1[s], y2[s], y);
+                for (int s = 0; s < VPL; ++s)
+                    if (s == s0 && (int)ln == l0) pos64(vt[s], y0[s], y1[s], y2[s], y);
+            } else {
+                if ((int)ln == l0) pos64(vt[s0], y0[s0], y1[s0], y2[s0], y);
+            }
             for (int c = 0; c < 3; ++c) ref[c] = __shfl(y[c], l0);
         }
+        // every neighbour must be a live vertex (its new number is then < nv;
+        // numbers left from dead vertices are not trusted)
+        bool bad = false;
+#pragma unroll
+        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
+            if ((alive[s] >> ln) & 1) {
+                const W a = va[s];
+#pragma unroll
+                for (int e = 0; e < 3; ++e) {
+                    const uint32_t u = T::fld(a, e);
+                    bad |= !is_alive(u);
+                }
+            }
+        }
+        if (ballot(bad)) return false;
         float4* vout = st.vert + (int64_t)slot * st.cap;
+        uint64_t* tri64 = st.tri64 ? st.tri64 + (int64_t)slot * st.cap : nullptr;
         const double p64[3] = {(double)px, (double)py, (double)pz};
 #pragma unroll
-        for (int s = 0; s < VPL; ++s) {
+        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
             if ((alive[s] >> ln) & 1) {
-                uint32_t t0 = M.ta[f10(vt[s], 0)], t1 = M.ta[f10(vt[s], 1)], t2 = M.ta[f10(vt[s], 2)];
-                uint32_t a0 = M.sor[f10(va[s], 0)], a1 = M.sor[f10(va[s], 1)], a2 = M.sor[f10(va[s], 2)];
-                const uint32_t v = vid[s];
-                M.vtri[v] = t0 | (t1 << 10) | (t2 << 20);
-                M.vadj[v] = a0 | (a1 << 10) | (a2 << 20);
+                const W t = vt[s], a = va[s];
+                uint32_t t0 = M.ta[T::fld(t, 0)], t1 = M.ta[T::fld(t, 1)], t2 = M.ta[T::fld(t, 2)];
+                uint32_t a0 = M.sor[T::fld(a, 0)], a1 = M.sor[T::fld(a, 1)], a2 = M.sor[T::fld(a, 2)];
+                const uint32_t v = M.sor[s * 64 + ln];
+                M.vtri[v] = T::pack3(t0, t1, t2);
+                M.vadj[v] = T::pack3(a0, a1, a2);
                 double y[3];
-                pos64(vt[s], y0[s], y1[s], y2[s], y);
+                pos64(t, y0[s], y1[s], y2[s], y);
                 M.vpx[v] = y[0] - ref[0];
                 M.vpy[v] = y[1] - ref[1];
                 M.vpz[v] = y[2] - ref[2];
@@ -914,23 +1133,24 @@ struct Cell {
                 if (u0 > u1) { tmp = u0; u0 = u1; u1 = tmp; }
                 if (u1 > u2) { tmp = u1; u1 = u2; u2 = tmp; }
                 if (u0 > u1) { tmp = u0; u0 = u1; u1 = tmp; }
+                const uint32_t packed = tri64 ? 0u : (u0 | (u1 << 10) | (u2 << 20));
                 vout[v] = make_float4((float)(p64[0] + y[0]), (float)(p64[1] + y[1]), (float)(p64[2] + y[2]),
-                                      __uint_as_float(u0 | (u1 << 10) | (u2 << 20)));
+                                      __uint_as_float(packed));
+                if (tri64) tri64[v] = (uint64_t)u0 | ((uint64_t)u1 << 21) | ((uint64_t)u2 << 42);
                 atomicAdd(&M.tb[t0], 1u);
                 atomicAdd(&M.tb[t1], 1u);
                 atomicAdd(&M.tb[t2], 1u);
-                atomicMin(&M.edge[t0], v);
-                atomicMin(&M.edge[t1], v);
-                atomicMin(&M.edge[t2], v);
+                atomicMin(&M.anchor[t0], v);
+                atomicMin(&M.anchor[t1], v);
+                atomicMin(&M.anchor[t2], v);
             }
         }
-        wave_sync();
+        sync();
         // facet rings in output (rank) order, counter-clockwise seen from outside;
         // sizes and anchors (lowest vertex) are indexed by facet rank
         uint16_t* fs = st.fsize + (int64_t)slot * st.cap;
         uint16_t* fvp = st.fv + (int64_t)slot * 3 * st.cap;
         uint32_t carry = 0;
-        bool bad = false;
         for (int r0 = 0; r0 < F; r0 += 64) {
             const uint32_t r = (uint32_t)(r0 + (int)ln);
             uint32_t sz = r < (uint32_t)F ? M.tb[r] : 0u;
@@ -941,7 +1161,7 @@ struct Cell {
             }
             if (r < (uint32_t)F) {
                 fs[r] = (uint16_t)sz;
-                const uint32_t base = carry + x - sz, start = M.edge[r];
+                const uint32_t base = carry + x - sz, start = M.anchor[r];
                 if (sz < 3 || start >= nv) {
                     bad = true;
                 } else {
@@ -949,9 +1169,9 @@ struct Cell {
                     do {
                         fvp[base + t] = (uint16_t)v;
                         ++t;
-                        uint32_t tri = M.vtri[v], adj = M.vadj[v];
-                        uint32_t k = f10(tri, 0) == r ? 0u : (f10(tri, 1) == r ? 1u : 2u);
-                        v = f10(adj, (k + 1) % 3);
+                        W tri = M.vtri[v], adj = M.vadj[v];
+                        uint32_t k = T::fld(tri, 0) == r ? 0u : (T::fld(tri, 1) == r ? 1u : 2u);
+                        v = T::fld(adj, (k + 1) % 3);
                     } while (v != start && t < sz && v < nv);
                     bad |= (v != start) || (t != sz);
                 }
@@ -964,11 +1184,11 @@ struct Cell {
         double vol6 = 0.0, mx = 0.0, my = 0.0, mz = 0.0;
         for (uint32_t v = ln; v < nv; v += 64) {
             const double Px = M.vpx[v], Py = M.vpy[v], Pz = M.vpz[v];
-            uint32_t tri = M.vtri[v], adj = M.vadj[v];
+            W tri = M.vtri[v], adj = M.vadj[v];
 #pragma unroll
             for (int k = 0; k < 3; ++k) {
-                uint32_t an = M.edge[f10(tri, k)];
-                uint32_t nx = f10(adj, (k + 1) % 3);
+                uint32_t an = M.anchor[T::fld(tri, k)];
+                uint32_t nx = T::fld(adj, (k + 1) % 3);
                 if (an == v || nx == an) continue;
                 const double Qx = M.vpx[an], Qy = M.vpy[an], Qz = M.vpz[an];
                 const double Nx = M.vpx[nx], Ny = M.vpy[nx], Nz = M.vpz[nx];
@@ -1019,24 +1239,24 @@ struct Cell {
     }
 };
 
-template <int VPL, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_clip(ClipArgs A) {
-    __shared__ WaveMem<VPL> mem[WAVES];
-    WaveMem<VPL>& M = mem[threadIdx.x >> 6];
+// The per-wave work loop shared by every tier.
+template <int VPL>
+__device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A) {
     Cell<VPL> C(M, A);
     const uint32_t count = A.list ? *A.list_count : (uint32_t)A.n;
     unsigned long long st_empty = 0, st_large = 0, st_unc = 0, st_fail = 0, st_fp64 = 0;
     for (;;) {
         uint32_t c = 0;
         if (C.ln == 0) c = atomicAdd(A.work_counter, 1u);
-        c = (uint32_t)__builtin_amdgcn_readfirstlane((int)c);
+        c = uni(c);
         if (c >= count) break;
         const uint32_t k = A.list ? A.list[c] : c;
         const uint32_t slot = A.list ? c : k;
         const uint32_t orig = A.order[k];
         // a cell is built with plain FP32 signs first (mixed mode: with FP64
         // re-evaluation of doubtful ones); if that meets an inconsistent
-        // configuration it is rebuilt once with the FP64 re-evaluation
+        // configuration it is rebuilt with the FP64 re-evaluation, then with
+        // every sign in FP64
         C.robust = A.precision == 2 ? 1 : 0;
         bool done = false, escalated = false, loser = false;
         for (int attempt = 0; attempt < 3 && !done; ++attempt) {
@@ -1082,7 +1302,7 @@ __global__ __launch_bounds__(64 * WAVES) void k_clip(ClipArgs A) {
         }
         if (escalated) continue;
         if (!done) {
-            // still inconsistent after the robust rebuild: report an empty cell
+            // still inconsistent after the robust rebuilds: report an empty cell
             C.write_empty(orig, kFlagFailed | kFlagUncertain);
             ++st_fail;
             ++st_empty;
@@ -1103,11 +1323,30 @@ __global__ __launch_bounds__(64 * WAVES) void k_clip(ClipArgs A) {
     }
 }
 
+// Register tiers: per-cell arrays in LDS, several independent waves per block.
+template <int VPL, int WAVES>
+__global__ __launch_bounds__(64 * WAVES) void k_clip(ClipArgs A) {
+    __shared__ WaveMem<VPL> mem[WAVES];
+    run_cells<VPL>(mem[threadIdx.x >> 6], A);
+}
+
+// Arena tier: one wave per block, its per-cell arrays in arena[blockIdx.x].
+constexpr int kArenaVPL = kTierCap[2] / 64;
+__global__ __launch_bounds__(64) void k_clip_arena(ClipArgs A, WaveMem<kArenaVPL>* arena) {
+    run_cells<kArenaVPL>(arena[blockIdx.x], A);
+}
+
+static_assert(kTierCap[0] == 64 && kTierCap[1] == 256, "register tiers are instantiated for 64 and 256 vertices");
+static_assert(Tier<kArenaVPL>::CAP <= (1 << Tier<kArenaVPL>::kB) && Tier<kArenaVPL>::CAP <= (1 << 16),
+              "arena-tier indices must fit their packings and the 16-bit staged facet lists");
+
 }  // namespace
+
+size_t arena_bytes_per_wave() { return sizeof(WaveMem<kArenaVPL>); }
 
 int clip_grid_waves(int tier, int num_cu) {
     int per_cu = 0;
-    hipError_t e;
+    hipError_t e = hipSuccess;
     if (tier == 0) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip<1, 4>, 256, 0);
         per_cu *= 4;
@@ -1115,13 +1354,13 @@ int clip_grid_waves(int tier, int num_cu) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip<4, 2>, 128, 0);
         per_cu *= 2;
     } else {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip<16, 1>, 64, 0);
+        per_cu = 2;  // arena waves: bounded by arena memory, not by occupancy
     }
     if (e != hipSuccess || per_cu < 1) per_cu = 4;
     return per_cu * num_cu;
 }
 
-hipError_t launch_clip(const ClipArgs& a, int grid_waves, hipStream_t s) {
+hipError_t launch_clip(const ClipArgs& a, int grid_waves, void* arena, hipStream_t s) {
     switch (a.tier) {
         case 0: {
             int blocks = (grid_waves + 3) / 4;
@@ -1134,7 +1373,9 @@ hipError_t launch_clip(const ClipArgs& a, int grid_waves, hipStream_t s) {
             break;
         }
         default:
-            hipLaunchKernelGGL((k_clip<16, 1>), dim3(grid_waves), dim3(64), 0, s, a);
+            if (!arena) return hipErrorInvalidValue;
+            hipLaunchKernelGGL(k_clip_arena, dim3(grid_waves), dim3(64), 0, s, a,
+                               static_cast<WaveMem<kArenaVPL>*>(arena));
             break;
     }
     return hipGetLastError();

@@ -145,9 +145,16 @@ __global__ __launch_bounds__(256) void k_write(WriteArgs a) {
                 a.vert[3 * (vo + v) + 2] = q.z;
             }
             if (a.vert_planes) {
-                a.vert_planes[3 * (vo + v)] = C[tri & 1023u];
-                a.vert_planes[3 * (vo + v) + 1] = C[(tri >> 10) & 1023u];
-                a.vert_planes[3 * (vo + v) + 2] = C[(tri >> 20) & 1023u];
+                uint32_t r0 = tri & 1023u, r1 = (tri >> 10) & 1023u, r2 = (tri >> 20) & 1023u;
+                if (st.tri64) {
+                    const uint64_t t = st.tri64[slot * cap + v];
+                    r0 = (uint32_t)(t & 0x1FFFFFu);
+                    r1 = (uint32_t)((t >> 21) & 0x1FFFFFu);
+                    r2 = (uint32_t)((t >> 42) & 0x1FFFFFu);
+                }
+                a.vert_planes[3 * (vo + v)] = C[r0];
+                a.vert_planes[3 * (vo + v) + 1] = C[r1];
+                a.vert_planes[3 * (vo + v) + 2] = C[r2];
             }
         }
         const int nbox = nf - nn;

@@ -12,6 +12,8 @@ namespace vd {
 constexpr int kMaxLeaf = 64;                 // leaf refs store count-1 in 6 bits
 constexpr int64_t kMaxSites = int64_t(1) << 25;  // leaf refs store `first` in 25 bits
 constexpr int kDefaultLeaf = 16;
+// Vertex (= plane) capacity of a cell in each clipping pass.
+constexpr int kTierCap[3] = {64, 256, 16384};
 
 // ---------------------------------------------------------------- BVH
 
@@ -45,13 +47,16 @@ __host__ __device__ inline uint32_t leaf_count(uint32_t r) { return ((r >> 25) &
 // Finished cells are written to fixed-capacity slots before the CSR pass.
 // Capacity `cap` = vertices = planes per cell; facet-vertex lists hold 3 cap.
 //   vert[slot*cap + v]   : global position xyz, .w = the vertex's three facet
-//                          ranks (ascending, 10 bits each) as raw bits
+//                          ranks (ascending, 10 bits each) as raw bits, unless
+//                          tri64 is set (cap > 1024)
+//   tri64[slot*cap + v]  : the three facet ranks, 21 bits each (or null)
 //   code[slot*cap + f]   : facet codes in ascending order (site ids, box -1..-6)
 //   fsize[slot*cap + f]  : vertices of facet f
 //   fv[slot*3cap + t]    : cell-local vertex indices of all facets, concatenated
 struct Stage {
     int cap;
     float4* vert;
+    uint64_t* tri64;
     int32_t* code;
     uint16_t* fsize;
     uint16_t* fv;
@@ -80,7 +85,7 @@ struct ClipArgs {
     int culling;              // 1 directional, 2 isotropic
     int traversal;            // 1 best-first, 2 depth-first
     int precision;            // 1 fp32, 2 mixed
-    int tier;                 // 0, 1, 2
+    int tier;                 // 0, 1, 2 (capacity kTierCap[tier])
     // work: cells c in [0, count) are list[c] (or c itself when list == null)
     uint32_t* work_counter;
     const uint32_t* list;
@@ -138,9 +143,11 @@ hipError_t launch_losers(float4* spts, const uint64_t* keys, const uint32_t* ord
                          hipStream_t s);
 hipError_t launch_karras(const uint64_t* keys, int64_t n, int2* child, int* parent_int, int* parent_leaf, int2* range,
                          hipStream_t s);
-hipError_t launch_bounds(const float4* spts, int64_t n, const int2* child, const int* parent_int,
-                         const int* parent_leaf, const int2* range, uint32_t* counters, Node* nodes, int leaf_size,
-                         hipStream_t s);
+// Child boxes and max weights of every internal node (range reductions over a
+// sparse table of 64-site block boxes; table: box_table_size(n) entries).
+size_t box_table_size(int64_t n);
+hipError_t launch_bounds(const float4* spts, int64_t n, const int2* child, const int2* range, NodeChild* table,
+                         Node* nodes, int leaf_size, hipStream_t s);
 
 // Exclusive scan of uint32 counts into int64 offsets [n+1] (out[n] = total).
 size_t scan_tmp_size(int64_t n);
@@ -148,8 +155,11 @@ hipError_t scan_counts(const uint32_t* in, int64_t n, int64_t* out, int64_t* tmp
 // Exclusive scan of uint32 -> uint32 (for radix histograms).
 hipError_t scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* tmp, hipStream_t s);
 
+// Waves to launch for a clipping pass, and the per-wave arena the last pass
+// (tier 2) needs: launch_clip(tier 2) takes grid_waves * arena_bytes_per_wave().
 int clip_grid_waves(int tier, int num_cu);
-hipError_t launch_clip(const ClipArgs& a, int grid_waves, hipStream_t s);
+size_t arena_bytes_per_wave();
+hipError_t launch_clip(const ClipArgs& a, int grid_waves, void* arena, hipStream_t s);
 hipError_t launch_set_i64(int64_t* dst, int64_t value, hipStream_t s);
 hipError_t launch_write(const WriteArgs& a, hipStream_t s);
 

@@ -329,59 +329,151 @@ hipError_t launch_karras(const uint64_t* keys, int64_t n, int2* child, int* pare
 }
 
 // ------------------------------------------------------------------ bounds
-// Bottom-up: one thread per site climbs towards the root; at each node the
-// first arrival stores its child record and stops, the second merges both
-// children and continues.  Children whose subtree holds <= leaf_size sites
-// are referenced as leaves.
+// Every node covers a contiguous range of sites in Morton order, so each
+// child's box and max weight is a reduction over that range.  Boxes of
+// aligned blocks of 64 sites are folded into a sparse table (level k holds
+// the box of 2^k consecutive blocks), and a range is its partial head and tail
+// blocks plus two overlapping table entries (min/max are idempotent).  No
+// atomics, no fences, no climb.
 
-__device__ inline float ld_coherent(const float* p) {
-    return __int_as_float(__hip_atomic_load((const int*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+struct BoxAcc {
+    float lo[3], hi[3], w;
+    __device__ void init() {
+        lo[0] = lo[1] = lo[2] = INFINITY;
+        hi[0] = hi[1] = hi[2] = -INFINITY;
+        w = -INFINITY;
+    }
+    __device__ void add(float4 p) {
+        lo[0] = fminf(lo[0], p.x); lo[1] = fminf(lo[1], p.y); lo[2] = fminf(lo[2], p.z);
+        hi[0] = fmaxf(hi[0], p.x); hi[1] = fmaxf(hi[1], p.y); hi[2] = fmaxf(hi[2], p.z);
+        w = fmaxf(w, p.w);
+    }
+    __device__ void add(const NodeChild& c) {
+        for (int k = 0; k < 3; ++k) {
+            lo[k] = fminf(lo[k], c.lo[k]);
+            hi[k] = fmaxf(hi[k], c.hi[k]);
+        }
+        w = fmaxf(w, c.wmax);
+    }
+    __device__ NodeChild out(uint32_t ref) const {
+        NodeChild c;
+        for (int k = 0; k < 3; ++k) {
+            c.lo[k] = lo[k];
+            c.hi[k] = hi[k];
+        }
+        c.wmax = w;
+        c.ref = ref;
+        return c;
+    }
+};
+
+__device__ inline float wave_min_f(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
+    return v;
+}
+__device__ inline float wave_max_f(float v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
+    return v;
 }
 
-__global__ void k_bounds(const float4* __restrict__ spts, int n, const int2* __restrict__ child,
-                         const int* __restrict__ parent_int, const int* __restrict__ parent_leaf,
-                         const int2* __restrict__ range, uint32_t* counters, Node* nodes, int leaf_size) {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= n) return;
-    float4 p = spts[k];
-    float lo[3] = {p.x, p.y, p.z}, hi[3] = {p.x, p.y, p.z};
-    float wm = p.w;
-    uint32_t ref = leaf_ref((uint32_t)k, 1u);
-    int cur = ~k;
-    int par = parent_leaf[k];
-    // a radix tree over 64-bit codes made unique by 32-bit positions is at
-    // most 96 levels deep; the bound only guards against a malformed tree
-    for (int depth = 0; par >= 0 && depth < 128; ++depth) {
-        int2 ch = child[par];
-        int slot = (ch.x == cur) ? 0 : 1;
-        NodeChild* dst = &nodes[par].c[slot];
-        float4* d4 = reinterpret_cast<float4*>(dst);
-        d4[0] = make_float4(lo[0], lo[1], lo[2], wm);
-        d4[1] = make_float4(hi[0], hi[1], hi[2], __uint_as_float(ref));
-        __threadfence();
-        uint32_t old = atomicAdd(&counters[par], 1u);
-        if (old == 0) return;
-        __threadfence();
-        const float* sib = reinterpret_cast<const float*>(&nodes[par].c[1 - slot]);
-        for (int c = 0; c < 3; ++c) {
-            lo[c] = fminf(lo[c], ld_coherent(sib + c));
-            hi[c] = fmaxf(hi[c], ld_coherent(sib + 4 + c));
-        }
-        wm = fmaxf(wm, ld_coherent(sib + 3));
-        int2 r = range[par];
-        uint32_t cnt = (uint32_t)(r.y - r.x + 1);
-        ref = (cnt <= (uint32_t)leaf_size) ? leaf_ref((uint32_t)r.x, cnt) : (uint32_t)par;
-        cur = par;
-        par = parent_int[par];
+// level 0: one wave per block of 64 sites
+__global__ __launch_bounds__(256) void k_block_boxes(const float4* __restrict__ spts, int64_t n,
+                                                     NodeChild* __restrict__ lvl0, int64_t nb) {
+    const int64_t b = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int ln = threadIdx.x & 63;
+    if (b >= nb) return;
+    const int64_t i = b * 64 + ln;
+    float4 p = i < n ? spts[i] : make_float4(INFINITY, INFINITY, INFINITY, -INFINITY);
+    float4 q = i < n ? p : make_float4(-INFINITY, -INFINITY, -INFINITY, -INFINITY);
+    float l0 = wave_min_f(p.x), l1 = wave_min_f(p.y), l2 = wave_min_f(p.z);
+    float h0 = wave_max_f(q.x), h1 = wave_max_f(q.y), h2 = wave_max_f(q.z), w = wave_max_f(q.w);
+    if (ln == 0) {
+        NodeChild c;
+        c.lo[0] = l0; c.lo[1] = l1; c.lo[2] = l2;
+        c.hi[0] = h0; c.hi[1] = h1; c.hi[2] = h2;
+        c.wmax = w;
+        c.ref = 0;
+        lvl0[b] = c;
     }
 }
 
-hipError_t launch_bounds(const float4* spts, int64_t n, const int2* child, const int* parent_int,
-                         const int* parent_leaf, const int2* range, uint32_t* counters, Node* nodes, int leaf_size,
-                         hipStream_t s) {
+// level k from level k-1: entry b covers blocks [b, b + 2^k)
+__global__ void k_sparse_level(const NodeChild* __restrict__ prev, NodeChild* __restrict__ cur, int64_t nb,
+                               int64_t half) {
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b + 2 * half > nb) return;
+    BoxAcc a;
+    a.init();
+    a.add(prev[b]);
+    a.add(prev[b + half]);
+    cur[b] = a.out(0);
+}
+
+__device__ inline int floor_log2(int64_t x) { return 63 - __clzll((long long)x); }
+
+__device__ NodeChild range_box(const float4* __restrict__ spts, const NodeChild* __restrict__ table, int64_t nb,
+                               int f, int l, uint32_t ref) {
+    BoxAcc a;
+    a.init();
+    const int64_t b0 = ((int64_t)f + 63) >> 6;      // first full block
+    const int64_t b1 = ((int64_t)l + 1) >> 6;       // one past the last full block
+    if (b1 <= b0 || l - f < 128) {
+        for (int i = f; i <= l; ++i) a.add(spts[i]);
+    } else {
+        for (int64_t i = f; i < b0 * 64; ++i) a.add(spts[i]);
+        for (int64_t i = b1 * 64; i <= l; ++i) a.add(spts[i]);
+        const int64_t cnt = b1 - b0;
+        const int k = floor_log2(cnt);
+        const NodeChild* lv = table + (int64_t)k * nb;
+        a.add(lv[b0]);
+        a.add(lv[b1 - (int64_t(1) << k)]);
+    }
+    return a.out(ref);
+}
+
+__global__ void k_node_boxes(const float4* __restrict__ spts, int n, const int2* __restrict__ child,
+                             const int2* __restrict__ range, const NodeChild* __restrict__ table, int64_t nb,
+                             Node* __restrict__ nodes, int leaf_size) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    int2 r = range[i];
+    if (r.y - r.x + 1 <= leaf_size) return;  // a leaf itself: never visited as a node
+    int2 ch = child[i];
+    for (int s = 0; s < 2; ++s) {
+        int c = s ? ch.y : ch.x;
+        int f, l;
+        if (c < 0) {
+            f = l = ~c;
+        } else {
+            int2 cr = range[c];
+            f = cr.x;
+            l = cr.y;
+        }
+        uint32_t cnt = (uint32_t)(l - f + 1);
+        uint32_t ref = cnt <= (uint32_t)leaf_size ? leaf_ref((uint32_t)f, cnt) : (uint32_t)c;
+        nodes[i].c[s] = range_box(spts, table, nb, f, l, ref);
+    }
+}
+
+size_t box_table_size(int64_t n) {
+    int64_t nb = (n + 63) / 64;
+    int levels = 1;
+    while ((int64_t(1) << levels) <= nb) ++levels;
+    return (size_t)levels * (size_t)nb;
+}
+
+hipError_t launch_bounds(const float4* spts, int64_t n, const int2* child, const int2* range, NodeChild* table,
+                         Node* nodes, int leaf_size, hipStream_t s) {
     if (n < 2) return hipSuccess;
-    hipLaunchKernelGGL(k_bounds, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, spts, (int)n, child, parent_int,
-                       parent_leaf, range, counters, nodes, leaf_size);
+    const int64_t nb = (n + 63) / 64;
+    hipLaunchKernelGGL(k_block_boxes, dim3((unsigned)((nb * 64 + 255) / 256)), dim3(256), 0, s, spts, n, table, nb);
+    int k = 1;
+    for (int64_t half = 1; 2 * half <= nb; half *= 2, ++k) {
+        hipLaunchKernelGGL(k_sparse_level, dim3((unsigned)((nb + 255) / 256)), dim3(256), 0, s,
+                           table + (int64_t)(k - 1) * nb, table + (int64_t)k * nb, nb, half);
+    }
+    hipLaunchKernelGGL(k_node_boxes, dim3((unsigned)((n - 1 + 255) / 256)), dim3(256), 0, s, spts, (int)n, child,
+                       range, table, nb, nodes, leaf_size);
     return hipGetLastError();
 }
 
