@@ -60,6 +60,8 @@ def _load():
         P = ctypes.c_void_p
         lib.orc_run.restype = P
         lib.orc_run.argtypes = [P, P, ctypes.c_int64, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int]
+        lib.orc_run64.restype = P
+        lib.orc_run64.argtypes = [P, P, ctypes.c_int64, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int]
         lib.orc_sizes.restype = None
         lib.orc_sizes.argtypes = [P, P]
         lib.orc_fetch.restype = None
@@ -80,23 +82,32 @@ def default_box(xyz: np.ndarray) -> np.ndarray:
     return np.concatenate([x.min(axis=0), x.max(axis=0)]).astype(np.float64)
 
 
-def cells(xyz, w=None, box=None, ids=None, margin: bool = True, threads: int = 0) -> dict:
+def cells(xyz, w=None, box=None, ids=None, margin: bool = True, threads: int = 0, fp64: bool = False) -> dict:
     """Compute the cells ``ids`` (default: all) of the power diagram of
-    (xyz, w) clipped to ``box`` = [xmin, ymin, zmin, xmax, ymax, zmax]."""
+    (xyz, w) clipped to ``box`` = [xmin, ymin, zmin, xmax, ymax, zmax].
+
+    By default sites, weights and box are FP32 values (as the library takes
+    them).  ``fp64=True`` takes all three as FP64 values instead (finite
+    differences perturb inputs below FP32 resolution)."""
     lib = _load()
-    xyz = np.ascontiguousarray(xyz, dtype=np.float32)
+    dt = np.float64 if fp64 else np.float32
+    xyz = np.ascontiguousarray(xyz, dtype=dt)
     n = xyz.shape[0]
     if w is not None:
-        w = np.ascontiguousarray(w, dtype=np.float32)
+        w = np.ascontiguousarray(w, dtype=dt)
         assert w.shape == (n,)
-    # the clip box is an FP32 input like the sites: use its FP32 value exactly
-    box = default_box(xyz) if box is None else np.asarray(box, dtype=np.float32).astype(np.float64)
+    if box is None:
+        box = np.concatenate([xyz.min(axis=0), xyz.max(axis=0)]).astype(np.float64)
+    else:
+        # the clip box is an input like the sites: use its value in their precision
+        box = np.asarray(box, dtype=dt).astype(np.float64)
     if ids is not None:
         ids = np.ascontiguousarray(ids, dtype=np.int64)
         m = ids.shape[0]
     else:
         m = n
-    h = lib.orc_run(_ptr(xyz), _ptr(w), n, _ptr(box), _ptr(ids), m, int(margin), int(threads))
+    run = lib.orc_run64 if fp64 else lib.orc_run
+    h = run(_ptr(xyz), _ptr(w), n, _ptr(box), _ptr(ids), m, int(margin), int(threads))
     if not h:
         raise ValueError("oracle rejected its input")
     try:

@@ -101,9 +101,11 @@ bool solve3(const Plane& A, const Plane& B, const Plane& C, double* y) {
     return true;
 }
 
+// Sites in FP64 (FP32 inputs are widened exactly; an FP64 entry point lets
+// finite differences perturb them below FP32 resolution).
 struct Input {
-    const float* xyz;
-    const float* w;  // may be null (Voronoi)
+    const double* xyz;
+    const double* w;  // may be null (Voronoi)
     int64_t n;
     double box[6];   // lo.xyz, hi.xyz
     std::vector<char> loser;  // coincident site whose cell is empty
@@ -512,12 +514,33 @@ double nearest_distance(const Input& in, const Builder& B, int64_t i) {
 
 extern "C" {
 
+static void* run_impl(const double* xyz, const double* w, int64_t n, const double* box, const int64_t* cells, int64_t m,
+                     int want_margin, int nthreads);
+
 // Compute cells `cells[0..m)` (all n cells if cells == NULL).  `box` is
 // [lo.xyz, hi.xyz] in FP64.  Returns an opaque handle, or NULL on bad input.
 // `want_margin` = 0 skips the robustness margin (faster).
 void* orc_run(const float* xyz, const float* w, int64_t n, const double* box, const int64_t* cells, int64_t m,
               int want_margin, int nthreads) {
     if (n <= 0 || !xyz || !box) return nullptr;
+    std::vector<double> x((size_t)(3 * n)), ww;
+    for (int64_t k = 0; k < 3 * n; ++k) x[(size_t)k] = (double)xyz[k];
+    if (w) {
+        ww.resize((size_t)n);
+        for (int64_t k = 0; k < n; ++k) ww[(size_t)k] = (double)w[k];
+    }
+    return run_impl(x.data(), w ? ww.data() : nullptr, n, box, cells, m, want_margin, nthreads);
+}
+
+// The same with FP64 sites and weights.
+void* orc_run64(const double* xyz, const double* w, int64_t n, const double* box, const int64_t* cells, int64_t m,
+                int want_margin, int nthreads) {
+    if (n <= 0 || !xyz || !box) return nullptr;
+    return run_impl(xyz, w, n, box, cells, m, want_margin, nthreads);
+}
+
+static void* run_impl(const double* xyz, const double* w, int64_t n, const double* box, const int64_t* cells, int64_t m,
+                     int want_margin, int nthreads) {
     Input in{xyz, w, n, {box[0], box[1], box[2], box[3], box[4], box[5]}, {}};
     // coincident sites: sort by position, the heaviest of each run of equal
     // positions (lowest index among equals) is the only one that keeps a cell

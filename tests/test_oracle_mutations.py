@@ -54,3 +54,36 @@ def test_planted_mistake_is_caught(name, tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=str(tmp_path),
                        timeout=600)
     assert r.returncode == 1, "mutant %s survived the pins:\n%s" % (name, r.stdout[-2000:])
+
+
+# Mistakes in the analytic gradient oracle (the transport of the volume and
+# moment integrals, the vertex solve, the chain to sites and weights).
+GRAD_MUTANTS = {
+    "moment_sign": ("dA[c] += -(alpha * AY + S @ gamma) / D", "dA[c] += -(alpha * AY - S @ gamma) / D"),
+    "weight_half_sign": ("add(c, gp, -0.5 * dB[c])", "add(c, gp, 0.5 * dB[c])"),
+    "vertex_normal_term": ("dA[c] += -g[k] * y[v]", "dA[c] += g[k] * y[v]"),
+    "centroid_quotient": ("alpha = g_vol - gc @ m / (V * V)", "alpha = g_vol"),
+    "box_face_sign": ("add(i, -dB[c] * a, 0.0)", "add(i, dB[c] * a, 0.0)"),
+    "transposed_solve": ("g = np.linalg.solve(M.T, gv[v])", "g = np.linalg.solve(M, gv[v])"),
+    "pyramid_moment": ("integ[c][1] / (4.0 * np.linalg.norm", "integ[c][1] / (3.0 * np.linalg.norm"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(GRAD_MUTANTS))
+def test_planted_gradient_mistake_is_caught(name, tmp_path):
+    src = open(os.path.join(ROOT, "oracle", "grad.py")).read()
+    old, new = GRAD_MUTANTS[name]
+    assert src.count(old) == 1, "mutation site moved"
+    pkg = tmp_path / "oracle"
+    pkg.mkdir()
+    for f in ("__init__.py", "brute.py", "vd_oracle.cpp"):
+        shutil.copy(os.path.join(ROOT, "oracle", f), pkg / f)
+    (pkg / "grad.py").write_text(src.replace(old, new))
+    subprocess.run(["g++", "-O1", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o",
+                    str(pkg / "liboracle.so"), str(pkg / "vd_oracle.cpp")], check=True)
+    code = ("import sys; sys.path.insert(0, %r); sys.path.insert(1, %r); import pytest; "
+            "sys.exit(pytest.main(['-q', '-x', '-p', 'no:cacheprovider', '--import-mode=append', %r]))"
+            % (str(tmp_path), ROOT, os.path.join(ROOT, "tests", "test_oracle_grad.py")))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=str(tmp_path),
+                       timeout=600)
+    assert r.returncode == 1, "mutant %s survived the pins:\n%s" % (name, r.stdout[-2000:])
