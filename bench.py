@@ -81,6 +81,10 @@ def parse():
     ap.add_argument("--culling", type=int, default=3)
     ap.add_argument("--traversal", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true",
+                    help="skip the mixed-precision and fwd+bwd legs")
+    ap.add_argument("--bwd-config", default="power_clustered_1m",
+                    help="workload of the fwd+bwd leg (differentiable power diagram)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="target CPU time of the oracle sample")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run one plain 256 MiB device copy (reference for HBM byte counters)")
@@ -119,6 +123,72 @@ def cpu_baseline(xyz, w, box, seconds: float) -> dict:
 
 def log(msg: str):
     print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def timed(step, steps: int, warmup: int) -> float:
+    """Mean milliseconds of `step` over `steps` runs after `warmup` runs,
+    bracketed by device synchronisation."""
+    import torch
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        step()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) * 1000.0 / steps
+
+
+def mixed_leg(ctx, tx, tw, bbox, kw, steps, warmup) -> dict:
+    """The same workload with mixed FP32/FP64 predicates."""
+    kw2 = dict(kw, precision=2)
+
+    def step():
+        ctx.write(ctx.build_sizes(tx, tw, bbox, **kw2))
+
+    ms = timed(step, steps, warmup)
+    sz = ctx.last_sizes
+    return {"value": tx.shape[0] / (ms / 1000.0), "unit": "cells/s", "ms_per_step": ms,
+            "precision": "mixed fp32/fp64", "cells_with_fp64": sz["n_fp64"], "uncertain": sz["n_uncertain"]}
+
+
+def fwd_bwd_leg(config: str, seed: int, kw, steps, warmup) -> dict:
+    import numpy as np
+    """One training step of the differentiable power diagram: forward
+    (build + volumes/centroids/vertices), the loss
+    L = sum_i (V_i - |B|/n)^2 + |c_i - p_i|^2 and its hand-written backward to
+    positions and weights."""
+    import torch
+    import paper_2605_06408_amd as vd
+    from paper_2605_06408_amd import workloads as wl
+    xyz, w, box = wl.make(config, seed)
+    n = len(xyz)
+    bvol = float(np.prod(np.asarray(box[3:]) - np.asarray(box[:3])))
+    x = torch.from_numpy(xyz).cuda().requires_grad_(True)
+    ww = torch.from_numpy(w).cuda().requires_grad_(True)
+    ctx = vd.Context(0)
+    bbox = [float(v) for v in box]
+
+    def fwd():
+        return vd.power_diagram(x, ww, bbox=bbox, context=ctx, **kw)
+
+    def step():
+        x.grad = None
+        ww.grad = None
+        d = fwd()
+        loss = ((d.vol - bvol / n) ** 2).sum() + ((d.centroid - x) ** 2).sum()
+        loss.backward()
+
+    ms_fwd = timed(lambda: fwd(), steps, warmup)
+    ms = timed(step, steps, warmup)
+    d = fwd()
+    loss = ((d.vol - bvol / n) ** 2).sum() + ((d.centroid - x) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    tm = ctx.timings() if kw.get("profile") else {}
+    return {"workload": config, "n": n, "value": n / (ms / 1000.0), "unit": "cells/s", "ms_per_step": ms,
+            "fwd_ms": ms_fwd, "fwd_value": n / (ms_fwd / 1000.0), "bwd_kernel_ms": tm.get("backward"),
+            "empty_cells": ctx.last_sizes["n_empty"], "dtype": "f32 in, f64 per-cell arithmetic"}
 
 
 def main():
@@ -197,6 +267,11 @@ def main():
         "counters": ctr,
         "sizes": sizes,
     }
+    if not args.no_extra:
+        log("mixed-precision leg")
+        out["mixed"] = mixed_leg(ctx, tx, tw, bbox, kw, args.steps, args.warmup)
+        log("fwd+bwd leg (%s)" % args.bwd_config)
+        out["fwd_bwd"] = fwd_bwd_leg(args.bwd_config, args.seed, dict(kw, profile=True), args.steps, args.warmup)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(xyz, w, box, args.cpu_seconds)

@@ -40,7 +40,7 @@ typedef enum {
     VD_ERR_INVALID_ARG = 1,  /* bad pointer, size, option or box; non-finite input */
     VD_ERR_HIP = 2,          /* a HIP runtime call failed */
     VD_ERR_OOM = 3,          /* device allocation failed */
-    VD_ERR_STATE = 4,        /* vd_write without a successful vd_build */
+    VD_ERR_STATE = 4,        /* vd_write / vd_backward without a successful vd_build */
     VD_ERR_CAPACITY = 5      /* some cell needed more than the largest capacity */
 } vd_status;
 
@@ -72,7 +72,8 @@ typedef struct vd_options {
 #define VD_PHASE_BUILD 4      /* the whole vd_build, first to last device operation */
 #define VD_PHASE_WRITE 5      /* vd_write (CSR write-out and copies) */
 #define VD_PHASE_CLIP_TIER1 6 /* the 256-vertex tier alone (part of VD_PHASE_CLIP_LARGE) */
-#define VD_PHASE_COUNT 7
+#define VD_PHASE_BACKWARD 7   /* vd_backward */
+#define VD_PHASE_COUNT 8
 
 /* Work units counted when vd_options.counters = 1.  vd_get_counters returns
  * them per capacity tier: entry k + VD_CTR_COUNT * t is unit k of tier t
@@ -166,11 +167,32 @@ VD_API vd_status vd_build(vd_context* ctx, const float* xyz, const float* w, int
  * from vd_build).  Stream-ordered, does not synchronise. */
 VD_API vd_status vd_write(vd_context* ctx, const vd_outputs* out, void* stream);
 
+/* Gradients of L = sum_i g_vol[i] V_i + g_cen[i] . c_i + sum_v g_vert[v] . x_v
+ * with respect to the site positions and weights of the last build, through
+ * its combinatorics (facets and vertex plane-triples held fixed; the
+ * derivatives of Sec. 3, Eq. 1 under a motion of the bisecting planes).  The
+ * cell records staged by vd_build are the checkpoint: nothing is clipped
+ * again, so the call is valid until the next vd_build on this context.
+ *   g_vol   device float[n], or NULL (zero)
+ *   g_cen   device float[n*3], or NULL
+ *   g_vert  device float[n_vert*3] in the vertex order of vd_write, or NULL
+ *   g_xyz   device float[n*3] out (original site order)
+ *   g_w     device float[n] out, or NULL to skip (computed also for Voronoi
+ *           builds, as the derivative at w = 0)
+ * An empty cell has V = 0 and c = p_i, so it passes g_cen[i] to its site.
+ * Stream-ordered, does not synchronise; the output is deterministic except
+ * where a facet is not listed back by its neighbour (FP32-undecidable
+ * configurations), whose share is added atomically.  VD_ERR_STATE without a
+ * build. */
+VD_API vd_status vd_backward(vd_context* ctx, const float* g_vol, const float* g_cen, const float* g_vert,
+                             float* g_xyz, float* g_w, void* stream);
+
 /* Counters of the last build (see vd_sizes); host call, no device work. */
 VD_API vd_status vd_get_sizes(const vd_context* ctx, vd_sizes* sizes);
 
-/* Per-phase times of the last build/write, ms[VD_PHASE_*]; needs
- * vd_options.profile = 1 on that build.  Waits for the recorded events. */
+/* Per-phase times of the last build/write/backward, ms[VD_PHASE_*]; needs
+ * vd_options.profile = 1 on that build (phases not run read 0).  Waits for
+ * the recorded events. */
 VD_API vd_status vd_get_timings(vd_context* ctx, float* ms, int32_t count);
 
 /* Work counters of the last build (up to 3 * VD_CTR_COUNT entries, see

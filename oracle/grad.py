@@ -75,6 +75,8 @@ def _facet_integrals(poly, a):
 def cell_partials(xyz, w, box, res, t, g_vol=0.0, g_cen=None, g_vert_fn=None):
     """Contributions of cell t of an oracle result to dL/dp and dL/dw, for
     L = g_vol V_i + g_cen . c_i + sum_v phi(x_v) with grad phi = g_vert_fn.
+    g_vert_fn(x [k,3], codes [k,3], i) gives the gradient on the cell's
+    vertices (positions, ascending plane codes, site).
     Returns {site: (dL/dp (3,), dL/dw)}."""
     i = int(res["ids"][t])
     cv = cell_view(res, t)
@@ -113,7 +115,7 @@ def cell_partials(xyz, w, box, res, t, g_vol=0.0, g_cen=None, g_vert_fn=None):
             dB[c] += (alpha * A + gamma @ AY) / D
             dA[c] += -(alpha * AY + S @ gamma) / D
     if g_vert_fn is not None:
-        gv = np.asarray(g_vert_fn(cv["vert"]), float)
+        gv = np.asarray(g_vert_fn(cv["vert"], cv["vert_code"], i), float)
         for v in range(len(y)):
             codes = [int(c) for c in cv["vert_code"][v]]
             M = np.array([planes[c][0] for c in codes])
@@ -134,7 +136,8 @@ def cell_partials(xyz, w, box, res, t, g_vol=0.0, g_cen=None, g_vert_fn=None):
 
 def backward(xyz, w, box, g_vol=None, g_cen=None, g_vert_fn=None, ids=None, fp64=False):
     """dL/dp [n,3] and dL/dw [n] for L = sum_i g_vol_i V_i + g_cen_i . c_i
-    + sum over all vertices phi(x) (grad phi = g_vert_fn, vectorised over rows).
+    + sum over all vertices phi(x) (grad phi = g_vert_fn(x, codes, i), see
+    ``cell_partials``).
 
     With ``ids`` the gradients are exact only at those sites: the cells of
     the sites and of all their neighbours are computed (a site's gradient
@@ -165,14 +168,18 @@ def backward(xyz, w, box, g_vol=None, g_cen=None, g_vert_fn=None, ids=None, fp64
 
 
 def loss_value(xyz, w, box, g_vol=None, g_cen=None, phi=None, fp64=True):
-    """L = sum_i g_vol_i V_i + g_cen_i . c_i + sum over all vertices phi(x):
-    the function whose gradient ``backward`` returns (for finite differences)."""
+    """L = sum_i g_vol_i V_i + g_cen_i . c_i + sum over all vertices
+    phi(x, codes, i): the function whose gradient ``backward`` returns (for
+    finite differences)."""
     res = cells(xyz, w, box, margin=False, fp64=fp64)
     L = 0.0
     if g_vol is not None:
         L += float(np.dot(g_vol, res["vol"]))
     if g_cen is not None:
         L += float(np.sum(g_cen * res["centroid"]))
-    if phi is not None and len(res["vert"]):
-        L += float(np.sum(phi(res["vert"])))
+    if phi is not None:
+        for t in range(len(res["ids"])):
+            v0, v1 = res["vert_off"][t], res["vert_off"][t + 1]
+            if v1 > v0:
+                L += float(np.sum(phi(res["vert"][v0:v1], res["vert_code"][v0:v1], int(res["ids"][t]))))
     return L

@@ -35,7 +35,7 @@ TRAVERSAL_DEPTH_FIRST = 2
 
 MAX_SITES = 1 << 25
 
-PHASES = ("lbvh", "clip", "clip_large", "scan", "build", "write", "clip_tier1")
+PHASES = ("lbvh", "clip", "clip_large", "scan", "build", "write", "clip_tier1", "backward")
 COUNTERS = ("classify", "new_vertex", "node_test", "site_test", "final_vertex", "clip", "clip_effective", "leaf",
             "ball_test")
 
@@ -108,6 +108,8 @@ def load_library():
             lib.vd_get_timings.argtypes = [P, ctypes.POINTER(ctypes.c_float), ctypes.c_int32]
             lib.vd_get_counters.restype = ctypes.c_int
             lib.vd_get_counters.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32]
+            lib.vd_backward.restype = ctypes.c_int
+            lib.vd_backward.argtypes = [P, P, P, P, P, P, P]
             _lib = lib
     return _lib
 
@@ -137,6 +139,7 @@ class Context:
         with torch.cuda.device(self.device):
             _check(self.lib.vd_create(self.device.index, ctypes.byref(h)), "vd_create")
         self.handle = h
+        self.generation = 0  # counts builds: a backward needs the build it follows
 
     def close(self):
         if getattr(self, "handle", None):
@@ -174,6 +177,9 @@ class Context:
         with torch.cuda.device(self.device):
             st = self.lib.vd_build(self.handle, _ptr(xyz), _ptr(w), n, hb, ctypes.byref(opt),
                                    ctypes.c_void_p(stream), ctypes.byref(sz))
+        self.generation += 1
+        self.n = n
+        self.last_sizes = sz.as_dict()
         if st == 5 and allow_failed:
             return sz
         _check(st, "vd_build")
@@ -221,6 +227,88 @@ class Context:
     def build(self, xyz, w=None, bbox=None, **kw) -> Diagram:
         sz = self.build_sizes(xyz, w, bbox, **kw)
         return self.write(sz)
+
+    def backward(self, g_vol=None, g_cen=None, g_vert=None, want_w=True):
+        """vd_backward over the last build: gradients of
+        sum g_vol V + g_cen . c + g_vert . x with respect to the sites (and
+        weights).  Returns (g_xyz [n, 3], g_w [n] or None)."""
+        import torch
+        dev = self.device
+        n = self.n
+
+        def arg(t, shape):
+            if t is None:
+                return None
+            if not (t.is_cuda and t.dtype == torch.float32 and tuple(t.shape) == shape):
+                raise ValueError("gradient must be a CUDA float32 tensor of shape %s" % (shape,))
+            return t.contiguous()
+
+        gv = arg(g_vol, (n,))
+        gc = arg(g_cen, (n, 3))
+        gx = None if g_vert is None else arg(g_vert, (g_vert.shape[0], 3))
+        g_xyz = torch.empty((n, 3), dtype=torch.float32, device=dev)
+        g_w = torch.empty(n, dtype=torch.float32, device=dev) if want_w else None
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        with torch.cuda.device(dev):
+            _check(self.lib.vd_backward(self.handle, _ptr(gv), _ptr(gc), _ptr(gx), _ptr(g_xyz), _ptr(g_w),
+                                        ctypes.c_void_p(stream)), "vd_backward")
+        self._keep_grad = (gv, gc, gx)
+        return g_xyz, g_w
+
+
+def _power_diagram_fn():
+    import torch
+
+    class PowerDiagramFn(torch.autograd.Function):
+        """Differentiable diagram: (xyz, w) -> every output field of vd_write;
+        volumes, centroids and vertices carry gradients (vd_backward), the
+        integer topology does not.  The forward's cell records stay in the
+        context as the checkpoint, so the backward must come before the next
+        build on that context."""
+
+        @staticmethod
+        def forward(ctx, xyz, w, bbox, context, options):
+            sz = context.build_sizes(xyz.detach(), None if w is None else w.detach(), bbox, **options)
+            d = context.write(sz)
+            ctx.context = context
+            ctx.generation = context.generation
+            ctx.has_w = w is not None
+            ctx.n_vert = sz.n_vert
+            ctx.set_materialize_grads(False)
+            outs = tuple(getattr(d, k) for k in OUTPUT_FIELDS)
+            ctx.mark_non_differentiable(*[t for k, t in zip(OUTPUT_FIELDS, outs)
+                                          if k not in ("vol", "centroid", "vert")])
+            ctx.sizes = d.sizes
+            return outs
+
+        @staticmethod
+        def backward(ctx, *grads):
+            g = dict(zip(OUTPUT_FIELDS, grads))
+            if ctx.context.generation != ctx.generation:
+                raise RuntimeError("the context was used for another build after this forward; give each "
+                                   "differentiable diagram its own Context until its backward has run")
+            if g["vol"] is None and g["centroid"] is None and g["vert"] is None:
+                return None, None, None, None, None
+            g_xyz, g_w = ctx.context.backward(g["vol"], g["centroid"], g["vert"], want_w=ctx.has_w)
+            return g_xyz, g_w, None, None, None
+
+    return PowerDiagramFn
+
+
+_fn_cache = {}
+
+
+def power_diagram(xyz, w=None, bbox=None, context: Context | None = None, **options) -> Diagram:
+    """Differentiable build: like ``build`` but ``vol``, ``centroid`` and
+    ``vert`` carry gradients to ``xyz`` and ``w`` (hand-written backward,
+    combinatorics held fixed).  Uses a fresh Context unless one is given."""
+    if "fn" not in _fn_cache:
+        _fn_cache["fn"] = _power_diagram_fn()
+    ctx = context if context is not None else Context(xyz.device)
+    outs = _fn_cache["fn"].apply(xyz, w, bbox, ctx, options)
+    d = dict(zip(OUTPUT_FIELDS, outs))
+    d["sizes"] = ctx.last_sizes
+    return Diagram(**d)
 
 
 _contexts: dict = {}

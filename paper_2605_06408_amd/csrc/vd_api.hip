@@ -37,16 +37,18 @@ struct vd_context {
         bpart, misc, loc, cnt_v, cnt_f, cnt_n, vol, cen, flags, offv, offf, offn, scan_tmp, list1, list2, stats, ctr;
     DevBuf st_vert[3], st_tri64[3], st_code[3], st_fsize[3], st_fv[3];
     DevBuf arena;  // per-wave cell arrays of the 16384-vertex pass
+    DevBuf bwd_facet, bwd_self, bwd_orphan;  // backward scratch
     // last build
     bool valid = false;
     int64_t n = 0;
     vd_sizes sizes{};
     const uint32_t* order = nullptr;
     int tier_slots[3] = {0, 0, 0};
-    // profiling: events e[0..6] bracket the build phases, e[7..8] the write
-    hipEvent_t ev[9] = {};
+    // profiling: events e[0..6] bracket the build phases, e[7..8] the write,
+    // e[9..10] the backward
+    hipEvent_t ev[11] = {};
     bool ev_ready = false;
-    bool profiled = false, write_profiled = false;
+    bool profiled = false, write_profiled = false, bwd_profiled = false;
     bool counted = false;
 };
 
@@ -151,7 +153,7 @@ VD_API void vd_destroy(vd_context* c) {
                      &c->child, &c->pint, &c->pleaf, &c->range, &c->counters, &c->nodes, &c->hist, &c->stmp,
                      &c->bbox, &c->bpart, &c->misc, &c->loc, &c->cnt_v, &c->cnt_f, &c->cnt_n, &c->vol, &c->cen,
                      &c->flags, &c->offv, &c->offf, &c->offn, &c->scan_tmp, &c->list1, &c->list2, &c->stats,
-                     &c->ctr, &c->arena};
+                     &c->ctr, &c->arena, &c->bwd_facet, &c->bwd_self, &c->bwd_orphan};
     for (DevBuf* b : all) release(*b);
     if (c->ev_ready)
         for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -202,6 +204,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     const bool prof = o.profile != 0;
     c->profiled = false;
     c->write_profiled = false;
+    c->bwd_profiled = false;
     c->counted = false;
     if (prof) VD_TRY(ensure_events(c));
 
@@ -432,7 +435,7 @@ VD_API vd_status vd_get_timings(vd_context* c, float* ms, int32_t count) {
     if (!c || !ms || count < 0) return fail(VD_ERR_INVALID_ARG, "vd_get_timings: bad argument");
     if (!c->valid || !c->profiled) return fail(VD_ERR_STATE, "vd_get_timings: last build was not profiled");
     VD_HIP(hipSetDevice(c->device));
-    float t[VD_PHASE_COUNT] = {0, 0, 0, 0, 0, 0, 0};
+    float t[VD_PHASE_COUNT] = {};
     VD_HIP(hipEventSynchronize(c->ev[5]));
     VD_HIP(hipEventElapsedTime(&t[VD_PHASE_LBVH], c->ev[0], c->ev[1]));
     VD_HIP(hipEventElapsedTime(&t[VD_PHASE_CLIP], c->ev[1], c->ev[2]));
@@ -444,7 +447,54 @@ VD_API vd_status vd_get_timings(vd_context* c, float* ms, int32_t count) {
         VD_HIP(hipEventSynchronize(c->ev[8]));
         VD_HIP(hipEventElapsedTime(&t[VD_PHASE_WRITE], c->ev[7], c->ev[8]));
     }
+    if (c->bwd_profiled) {
+        VD_HIP(hipEventSynchronize(c->ev[10]));
+        VD_HIP(hipEventElapsedTime(&t[VD_PHASE_BACKWARD], c->ev[9], c->ev[10]));
+    }
     for (int k = 0; k < count && k < VD_PHASE_COUNT; ++k) ms[k] = t[k];
+    return VD_OK;
+}
+
+VD_API vd_status vd_backward(vd_context* c, const float* g_vol, const float* g_cen, const float* g_vert,
+                             float* g_xyz, float* g_w, void* stream) {
+    g_err.clear();
+    if (!c || !g_xyz) return fail(VD_ERR_INVALID_ARG, "vd_backward: null argument");
+    if (!c->valid) return fail(VD_ERR_STATE, "vd_backward: no successful build");
+    VD_HIP(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = c->n;
+    const size_t nf = (size_t)(c->sizes.n_facet > 0 ? c->sizes.n_facet : 1);
+    VD_TRY(ensure(c->bwd_facet, nf * sizeof(double4)));
+    VD_TRY(ensure(c->bwd_self, (size_t)n * sizeof(double4)));
+    VD_TRY(ensure(c->bwd_orphan, (size_t)n * 4 * sizeof(double)));
+    const bool prof = c->profiled;
+    if (prof) VD_HIP(hipEventRecord(c->ev[9], s));
+    VD_HIP(hipMemsetAsync(c->bwd_orphan.p, 0, (size_t)n * 4 * sizeof(double), s));
+    vd::BwdArgs a{};
+    a.n = n;
+    a.pts = as<float4>(c->spts);
+    a.inv = as<uint32_t>(c->inv);
+    a.loc = as<uint32_t>(c->loc);
+    for (int t = 0; t < 3; ++t) a.stage[t] = stage_of(c, t);
+    a.cnt_v = as<uint32_t>(c->cnt_v);
+    a.cnt_f = as<uint32_t>(c->cnt_f);
+    a.cnt_n = as<uint32_t>(c->cnt_n);
+    a.off_v = as<int64_t>(c->offv);
+    a.off_f = as<int64_t>(c->offf);
+    a.bbox = as<float>(c->bbox);
+    a.g_vol = g_vol;
+    a.g_cen = g_cen;
+    a.g_vert = g_vert;
+    a.gf = as<double4>(c->bwd_facet);
+    a.gself = as<double4>(c->bwd_self);
+    a.orphan = as<double>(c->bwd_orphan);
+    a.g_xyz = g_xyz;
+    a.g_w = g_w;
+    VD_HIP(vd::launch_backward(a, s));
+    if (prof) {
+        VD_HIP(hipEventRecord(c->ev[10], s));
+        c->bwd_profiled = true;
+    }
     return VD_OK;
 }
 

@@ -123,6 +123,31 @@ struct WriteArgs {
     int32_t* vert_planes;
 };
 
+// Inputs and outputs of the backward pass over the last build.
+struct BwdArgs {
+    int64_t n;
+    const float4* pts;        // sites in Morton order: x, y, z, w
+    const uint32_t* inv;      // original index -> Morton position
+    const uint32_t* loc;      // staged record of each cell, by Morton position
+    Stage stage[3];
+    const uint32_t* cnt_v;    // by original index
+    const uint32_t* cnt_f;
+    const uint32_t* cnt_n;
+    const int64_t* off_v;     // vertex and facet CSR offsets of the build
+    const int64_t* off_f;
+    const float* bbox;        // device [6]
+    const float* g_vol;       // [n] or null
+    const float* g_cen;       // [3n] or null
+    const float* g_vert;      // [3 n_vert] or null
+    // FP64 scratch: shares of neighbouring cells cancel to a much smaller
+    // site gradient wherever cells are thin, so they are kept and summed in FP64
+    double4* gf;              // [n_facet]: what a cell sends to its facet's site (dp xyz, dw)
+    double4* gself;           // [n]: each cell's share for its own site
+    double* orphan;           // [4n], zeroed: shares of facets not listed back
+    float* g_xyz;             // [3n] out
+    float* g_w;               // [n] out, or null
+};
+
 // ---------------------------------------------------------------- launches
 // (host wrappers; each returns the hipError_t of its launch)
 
@@ -162,5 +187,6 @@ size_t arena_bytes_per_wave();
 hipError_t launch_clip(const ClipArgs& a, int grid_waves, void* arena, hipStream_t s);
 hipError_t launch_set_i64(int64_t* dst, int64_t value, hipStream_t s);
 hipError_t launch_write(const WriteArgs& a, hipStream_t s);
+hipError_t launch_backward(const BwdArgs& a, hipStream_t s);
 
 }  // namespace vd

@@ -26,7 +26,8 @@ def lib():
 
 def test_header_declares_the_boundary():
     syms = declared_symbols()
-    for s in ["vd_create", "vd_destroy", "vd_build", "vd_write", "vd_get_sizes", "vd_last_error", "vd_version"]:
+    for s in ["vd_create", "vd_destroy", "vd_build", "vd_write", "vd_backward", "vd_get_sizes", "vd_last_error",
+              "vd_version"]:
         assert s in syms
 
 
@@ -52,6 +53,7 @@ def test_null_arguments_are_rejected_on_the_host(lib):
     assert lib.vd_write(None, None, None) == 1
     assert lib.vd_get_sizes(None, None) == 1
     assert lib.vd_create(0, None) == 1
+    assert lib.vd_backward(None, None, None, None, None, None, None) == 1
     lib.vd_destroy(None)  # no-op
 
 

@@ -1,0 +1,238 @@
+"""GPU backward (vd_backward, the autograd Function) against the FP64
+analytic gradient oracle, which finite differences pin on the CPU.
+
+Bar: the gradient is defined through the combinatorics, so it is compared on
+sites whose own cell and every neighbouring cell have the same combinatorics
+on both sides (same neighbours, facets and vertex plane-triples); those must
+be at least 90% of the sites (forward parity makes them almost all), and on
+them each gradient component agrees within GRAD_TOL relative to the site's
+gradient size plus the mean gradient size.
+The GPU evaluates every cell in FP64 from the same FP32 inputs and sums the
+shares of a site in FP64, rounding once to FP32 (2^-24 relative); around the
+thin cells of tight clusters those shares are up to ~1e8 times the site
+gradient they cancel to, which costs 1e8 * 2^-53 ~ 1e-8 in FP64.  GRAD_TOL
+leaves room for both with a wide margin."""
+import numpy as np
+import pytest
+
+from paper_2605_06408_amd import workloads as wl
+
+from .parity import gpu_build
+
+pytestmark = pytest.mark.gpu
+
+GRAD_TOL = 5e-5
+
+
+def _key_grad(codes, cell):
+    """Gradient on each vertex, keyed by (cell, ascending plane codes) so that
+    both sides get bit-identical values (FP32): a vertex's gradient must not
+    depend on its computed position, since a near-singular vertex solve
+    amplifies any difference in it."""
+    c = np.asarray(codes, np.int64).reshape(-1, 3)
+    key = (c * np.array([3, 5, 7])).sum(axis=1) + 11 * np.asarray(cell, np.int64)
+    return np.stack([np.sin(key), np.cos(key), np.sin(2.0 * key)], axis=1).astype(np.float32)
+
+
+def _key_grad_oracle(x, codes, i):
+    return _key_grad(codes, np.full(len(x), i)).astype(np.float64)
+
+
+def _topology(res, t, gpu):
+    """(neighbours, facet codes, sorted vertex plane-triples) of row t."""
+    nb = tuple(res["nbr"][res["nbr_off"][t]:res["nbr_off"][t + 1]].tolist())
+    fc = tuple(res["facet_nbr" if gpu else "facet_code"][res["facet_off"][t]:res["facet_off"][t + 1]].tolist())
+    vc = res["vert_planes" if gpu else "vert_code"][res["vert_off"][t]:res["vert_off"][t + 1]]
+    vt = tuple(sorted(tuple(int(c) for c in sorted(r)) for r in np.asarray(vc).reshape(-1, 3)))
+    return nb, fc, vt
+
+
+def _same_topology_sites(d, res, sites):
+    """Sites among `sites` whose gradient both sides assemble from the same
+    cells with identical combinatorics: the site's cell, its neighbours' cells
+    (oracle) and every cell that lists it on the GPU must match between the
+    GPU (Diagram d) and the oracle result `res` (which must hold the cells of
+    the sites and of their neighbours)."""
+    from .parity import to_numpy
+    row = {int(i): t for t, i in enumerate(res["ids"])}
+    need = np.array(sorted(row), np.int64)
+    d = d._replace(**{k: getattr(d, k).detach() for k in ("vol", "centroid", "vert")})
+    g = to_numpy(d, need)
+    grow = {int(i): t for t, i in enumerate(g["ids"])}
+    same = {i: _topology(g, grow[i], True) == _topology(res, row[i], False) for i in row}
+    # cells that list each site on the GPU (a cell sends a share to every
+    # site it lists, whether or not that site lists it back)
+    nbr_off = d.nbr_off.cpu().numpy()
+    nbr = d.nbr.cpu().numpy()
+    rows = np.repeat(np.arange(len(nbr_off) - 1), np.diff(nbr_off))
+    want = np.isin(nbr, np.asarray(sites, np.int64))
+    listers = {}
+    for i, j in zip(rows[want].tolist(), nbr[want].tolist()):
+        listers.setdefault(j, []).append(i)
+    out = []
+    for j in sites:
+        t = row[int(j)]
+        nb = res["nbr"][res["nbr_off"][t]:res["nbr_off"][t + 1]]
+        if (same[int(j)] and all(same.get(int(i), False) for i in nb)
+                and all(same.get(int(i), False) for i in listers.get(int(j), []))):
+            out.append(int(j))
+    return np.array(out, np.int64)
+
+
+def _compare(g_gpu, g_orc, sites):
+    g_gpu = np.asarray(g_gpu, np.float64)
+    g_orc = np.asarray(g_orc, np.float64)
+    if g_orc.ndim == 1:
+        g_gpu, g_orc = g_gpu[:, None], g_orc[:, None]
+    scale = np.abs(g_orc[sites]).max(axis=1) + np.abs(g_orc[sites]).max(axis=1).mean()
+    err = np.abs(g_gpu[sites] - g_orc[sites]).max(axis=1) / scale
+    return err
+
+
+def _run_backward(xyz, w, box, g_vol, g_cen, with_vert):
+    import torch
+    import paper_2605_06408_amd as vd
+    ctx = vd.Context(0)
+    x = torch.from_numpy(xyz).cuda()
+    ww = None if w is None else torch.from_numpy(w).cuda()
+    d = ctx.build(x, ww, bbox=[float(v) for v in box])
+    gv = torch.from_numpy(g_vol.astype(np.float32)).cuda()
+    gc = torch.from_numpy(g_cen.astype(np.float32)).cuda()
+    gx = None
+    if with_vert:
+        vp = d.vert_planes.cpu().numpy()
+        cell = np.repeat(np.arange(len(xyz)), np.diff(d.vert_off.cpu().numpy()))
+        gx = torch.from_numpy(_key_grad(vp, cell)).cuda()
+    g_xyz, g_w = ctx.backward(gv, gc, gx, want_w=True)
+    torch.cuda.synchronize()
+    return d, g_xyz.cpu().numpy(), g_w.cpu().numpy(), ctx
+
+
+@pytest.mark.parametrize("name,with_vert", [("uniform", False), ("uniform", True), ("power_uniform", False),
+                                            ("power_uniform", True), ("clustered", True)])
+def test_backward_matches_oracle(oracle_mod, name, with_vert):
+    from oracle import grad as og
+    n = 3000
+    xyz, w, box = getattr(wl, name)(n, 5)
+    rng = np.random.default_rng(9)
+    g_vol = rng.normal(size=n) * n
+    g_cen = rng.normal(size=(n, 3))
+    d, gp, gw, _ = _run_backward(xyz, w, box, g_vol, g_cen, with_vert)
+    op, ow, res = og.backward(xyz, w, box, g_vol, g_cen, _key_grad_oracle if with_vert else None)
+    sites = _same_topology_sites(d, res, np.arange(n))
+    assert len(sites) >= 0.9 * n
+    e = _compare(gp, op, sites)
+    print("%s vert=%s: %d sites, max rel err %.2e" % (name, with_vert, len(sites), e.max()))
+    assert e.max() <= GRAD_TOL
+    if w is not None:
+        ew = _compare(gw, ow, sites)
+        assert ew.max() <= GRAD_TOL
+
+
+def test_two_sites_closed_form_on_gpu():
+    # dV0/dw1 = -A / (2 D) = -1 and dV0/dw0 = +1; dV0/dx0 = 1/2 + (w0 - w1)/(2 D^2)
+    xyz = np.array([[0.25, 0.5, 0.5], [0.75, 0.5, 0.5]], np.float32)
+    w = np.array([0.0625, 0.0], np.float32)
+    box = np.array([0, 0, 0, 1, 1, 1.0])
+    _, gp, gw, _ = _run_backward(xyz, w, box, np.array([1.0, 0.0]), np.zeros((2, 3)), False)
+    assert gw == pytest.approx([1.0, -1.0], abs=1e-6)
+    assert gp[0] == pytest.approx([0.5 + 0.0625 / 0.5, 0, 0], abs=1e-6)
+    assert gp[1] == pytest.approx([0.5 - 0.0625 / 0.5, 0, 0], abs=1e-6)
+
+
+def test_empty_cells_pass_the_centroid_gradient():
+    # an empty power cell has c = p_i: its site receives g_cen[i] and nothing else
+    xyz = np.array([[0.3, 0.5, 0.5], [0.32, 0.5, 0.5], [0.8, 0.4, 0.6], [0.6, 0.8, 0.3]], np.float32)
+    w = np.array([0.05, 0.0, 0.0, 0.01], np.float32)
+    box = np.array([0, 0, 0, 1, 1, 1.0])
+    g_cen = np.arange(12, dtype=float).reshape(4, 3) / 10.0
+    d, gp, gw, _ = _run_backward(xyz, w, box, np.array([0.3, -1.0, 0.7, 0.2]), g_cen, False)
+    assert int(d.flags[1].item()) & 1
+    assert gp[1] == pytest.approx(g_cen[1], abs=1e-6)
+    from oracle import grad as og
+    op, ow, _ = og.backward(xyz, w, box, np.array([0.3, -1.0, 0.7, 0.2]), g_cen)
+    np.testing.assert_allclose(gp, op, rtol=1e-5, atol=1e-5)
+    np.testing.assert_allclose(gw, ow, rtol=1e-5, atol=1e-5)
+
+
+def test_backward_is_deterministic():
+    import torch
+    xyz, w, box = wl.power_uniform(5000, 2)
+    rng = np.random.default_rng(1)
+    g_vol = rng.normal(size=5000)
+    g_cen = rng.normal(size=(5000, 3))
+    _, gp1, gw1, ctx = _run_backward(xyz, w, box, g_vol, g_cen, True)
+    gv = torch.from_numpy(g_vol.astype(np.float32)).cuda()
+    gc = torch.from_numpy(g_cen.astype(np.float32)).cuda()
+    g2, w2 = ctx.backward(gv, gc, None)
+    _, gp3, gw3, _ = _run_backward(xyz, w, box, g_vol, g_cen, True)
+    assert np.array_equal(gp1, gp3) and np.array_equal(gw1, gw3)
+    assert not np.array_equal(gp1, g2.cpu().numpy())  # the vertex term matters
+
+
+def test_autograd_function_config5_loss(oracle_mod):
+    """loss = sum_i (V_i - |B|/n)^2 + |c_i - p_i|^2 through torch autograd."""
+    import torch
+    import paper_2605_06408_amd as vd
+    from oracle import grad as og
+    n = 2000
+    xyz, w, box = wl.power_clustered(n, 3)
+    x = torch.from_numpy(xyz).cuda().requires_grad_(True)
+    ww = torch.from_numpy(w).cuda().requires_grad_(True)
+    d = vd.power_diagram(x, ww, bbox=[float(v) for v in box])
+    loss = ((d.vol - 1.0 / n) ** 2).sum() + ((d.centroid - x) ** 2).sum()
+    loss.backward()
+    gp, gw = x.grad.cpu().numpy(), ww.grad.cpu().numpy()
+    vol = d.vol.detach().double().cpu().numpy()
+    cen = d.centroid.detach().double().cpu().numpy()
+    g_vol = 2.0 * (vol - 1.0 / n)
+    g_cen = 2.0 * (cen - xyz.astype(np.float64))
+    op, ow, res = og.backward(xyz, w, box, g_vol, g_cen)
+    op = op - g_cen  # the loss's own explicit -p term
+    sites = _same_topology_sites(d, res, np.arange(n))
+    assert len(sites) >= 0.9 * n
+    assert _compare(gp, op, sites).max() <= GRAD_TOL
+    assert _compare(gw, ow, sites).max() <= GRAD_TOL
+
+
+def test_backward_after_another_build_is_refused():
+    import torch
+    import paper_2605_06408_amd as vd
+    xyz, w, box = wl.power_uniform(500, 1)
+    ctx = vd.Context(0)
+    x = torch.from_numpy(xyz).cuda().requires_grad_(True)
+    d = vd.power_diagram(x, None, bbox=[float(v) for v in box], context=ctx)
+    ctx.build(x.detach(), None, bbox=[float(v) for v in box])
+    with pytest.raises(RuntimeError, match="another build"):
+        d.vol.sum().backward()
+
+
+def test_backward_power_clustered_million_sampled(oracle_mod):
+    """The differentiable power diagram of 1M clustered sites: the backward in
+    the configuration bench.py times, sampled sites against the oracle."""
+    import torch
+    from oracle import grad as og
+    xyz, w, box = wl.make("power_clustered_1m", 0)
+    n = len(xyz)
+    rng = np.random.default_rng(4)
+    d = gpu_build(xyz, w, box)
+    vol = d.vol.double().cpu().numpy()
+    cen = d.centroid.double().cpu().numpy()
+    g_vol = 2.0 * (vol - 1.0 / n)
+    g_cen = 2.0 * (cen - xyz.astype(np.float64))
+    import paper_2605_06408_amd as vd
+    ctx = vd.context(d.vol.device)
+    g_xyz, g_w = ctx.backward(torch.from_numpy(g_vol.astype(np.float32)).cuda(),
+                              torch.from_numpy(g_cen.astype(np.float32)).cuda())
+    gp, gw = g_xyz.cpu().numpy(), g_w.cpu().numpy()
+    flags = d.flags.cpu().numpy()
+    # half the sample from non-empty cells (most clustered cells are empty)
+    nonempty = np.nonzero((flags & 1) == 0)[0]
+    ids = np.unique(np.concatenate([rng.choice(n, 60, replace=False), rng.choice(nonempty, 60, replace=False)]))
+    op, ow, res = og.backward(xyz, w, box, g_vol, g_cen, ids=ids)
+    sites = _same_topology_sites(d, res, ids)
+    assert len(sites) >= 0.9 * len(ids)
+    e = _compare(gp, op, sites)
+    ew = _compare(gw, ow, sites)
+    print("1M sampled: %d sites, max rel err %.2e / %.2e" % (len(sites), e.max(), ew.max()))
+    assert e.max() <= GRAD_TOL and ew.max() <= GRAD_TOL

@@ -10,15 +10,19 @@ from oracle import grad as og
 BOX = np.array([0.0, 0.0, 0.0, 1.0, 1.0, 1.0])
 
 
-def _phi(x):
-    # a smooth vertex loss with a non-trivial gradient
-    return 0.5 * np.sum((x - 0.3) ** 2, axis=1) + np.sin(3.0 * x[:, 0])
+def _phi(x, codes, i):
+    # a smooth vertex loss with a non-trivial gradient, plus a term linear in
+    # each vertex with a coefficient keyed by the vertex (cell, planes)
+    key = (np.asarray(codes, np.int64) * np.array([3, 5, 7])).sum(axis=1) + 11 * i
+    lin = np.stack([np.sin(key), np.cos(key), np.sin(2.0 * key)], axis=1)
+    return 0.5 * np.sum((x - 0.3) ** 2, axis=1) + np.sin(3.0 * x[:, 0]) + np.sum(lin * x, axis=1)
 
 
-def _dphi(x):
+def _dphi(x, codes, i):
+    key = (np.asarray(codes, np.int64) * np.array([3, 5, 7])).sum(axis=1) + 11 * i
     g = x - 0.3
     g[:, 0] += 3.0 * np.cos(3.0 * x[:, 0])
-    return g
+    return g + np.stack([np.sin(key), np.cos(key), np.sin(2.0 * key)], axis=1)
 
 
 def _problem(n, seed, weighted):
