@@ -67,7 +67,7 @@ typedef struct vd_options {
 /* Phases reported by vd_get_timings (milliseconds, HIP events on `stream`). */
 #define VD_PHASE_LBVH 0       /* packing, Morton codes, radix sort, tree, bounds */
 #define VD_PHASE_CLIP 1       /* traversal + clipping, 64-vertex tier (one kernel) */
-#define VD_PHASE_CLIP_LARGE 2 /* traversal + clipping, 256- and 16384-vertex tiers */
+#define VD_PHASE_CLIP_LARGE 2 /* traversal + clipping, 256-, 1024- and 16384-vertex tiers */
 #define VD_PHASE_SCAN 3       /* prefix sums of the per-cell counts */
 #define VD_PHASE_BUILD 4      /* the whole vd_build, first to last device operation */
 #define VD_PHASE_WRITE 5      /* vd_write (CSR write-out and copies) */
@@ -77,7 +77,8 @@ typedef struct vd_options {
 
 /* Work units counted when vd_options.counters = 1.  vd_get_counters returns
  * them per capacity tier: entry k + VD_CTR_COUNT * t is unit k of tier t
- * (t = 0: 64 vertices, 1: 256, 2: 16384). */
+ * (t = 0: 64 vertices, 1: 256, 2: 1024, 3: 16384; VD_TIERS tiers). */
+#define VD_TIERS 4
 #define VD_CTR_CLASSIFY 0     /* vertex-versus-plane side tests */
 #define VD_CTR_NEW_VERTEX 1   /* vertices created by clipping */
 #define VD_CTR_NODE_TEST 2    /* BVH child-box tests (Sec. 4.2.2) */
@@ -87,7 +88,15 @@ typedef struct vd_options {
 #define VD_CTR_CLIP_EFFECTIVE 6 /* clips that changed the cell */
 #define VD_CTR_LEAF 7         /* leaves visited */
 #define VD_CTR_BALL 8         /* vertex-versus-node-box power-ball tests (culling 3) */
-#define VD_CTR_COUNT 9
+#define VD_CTR_FP64 9         /* vertex side tests re-evaluated in FP64 (of VD_CTR_CLASSIFY) */
+/* Shader clock cycles the waves spent (summed over waves, wall time of each
+ * wave, so stalls included): the whole traversal of a cell, the leaves within
+ * it, the clips within those, and finalizing the cell. */
+#define VD_CTR_CYC_TRAVERSE 10
+#define VD_CTR_CYC_LEAF 11
+#define VD_CTR_CYC_CLIP 12
+#define VD_CTR_CYC_FINAL 13
+#define VD_CTR_COUNT 14
 
 /* Result sizes of the last vd_build. */
 typedef struct vd_sizes {
@@ -195,7 +204,7 @@ VD_API vd_status vd_get_sizes(const vd_context* ctx, vd_sizes* sizes);
  * the recorded events. */
 VD_API vd_status vd_get_timings(vd_context* ctx, float* ms, int32_t count);
 
-/* Work counters of the last build (up to 3 * VD_CTR_COUNT entries, see
+/* Work counters of the last build (up to VD_TIERS * VD_CTR_COUNT entries, see
  * VD_CTR_*); needs vd_options.counters = 1. */
 VD_API vd_status vd_get_counters(const vd_context* ctx, uint64_t* out, int32_t count);
 

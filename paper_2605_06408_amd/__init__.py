@@ -34,10 +34,11 @@ TRAVERSAL_BEST_FIRST = 1
 TRAVERSAL_DEPTH_FIRST = 2
 
 MAX_SITES = 1 << 25
+TIERS = 4  # capacity tiers: 64, 256, 1024, 16384 vertices per cell
 
 PHASES = ("lbvh", "clip", "clip_large", "scan", "build", "write", "clip_tier1", "backward")
 COUNTERS = ("classify", "new_vertex", "node_test", "site_test", "final_vertex", "clip", "clip_effective", "leaf",
-            "ball_test")
+            "ball_test", "fp64_test", "cycles_traverse", "cycles_leaf", "cycles_clip", "cycles_final")
 
 STATUS = {0: "VD_OK", 1: "VD_ERR_INVALID_ARG", 2: "VD_ERR_HIP", 3: "VD_ERR_OOM", 4: "VD_ERR_STATE",
           5: "VD_ERR_CAPACITY"}
@@ -215,13 +216,14 @@ class Context:
 
     def counters(self) -> dict:
         """Work counters of the last build made with counters=True: a dict per
-        capacity tier ("tier0", "tier1", "tier2") and their sum ("total")."""
+        capacity tier ("tier0" .. "tier3": 64, 256, 1024, 16384 vertices) and
+        their sum ("total")."""
         k = len(COUNTERS)
-        v = (ctypes.c_uint64 * (3 * k))()
-        _check(self.lib.vd_get_counters(self.handle, v, 3 * k), "vd_get_counters")
+        v = (ctypes.c_uint64 * (TIERS * k))()
+        _check(self.lib.vd_get_counters(self.handle, v, TIERS * k), "vd_get_counters")
         vals = [int(x) for x in v]
-        out = {"tier%d" % t: dict(zip(COUNTERS, vals[t * k:(t + 1) * k])) for t in range(3)}
-        out["total"] = {c: sum(out["tier%d" % t][c] for t in range(3)) for c in COUNTERS}
+        out = {"tier%d" % t: dict(zip(COUNTERS, vals[t * k:(t + 1) * k])) for t in range(TIERS)}
+        out["total"] = {c: sum(out["tier%d" % t][c] for t in range(TIERS)) for c in COUNTERS}
         return out
 
     def build(self, xyz, w=None, bbox=None, **kw) -> Diagram:

@@ -34,16 +34,17 @@ struct vd_context {
     int num_cu = 0;
     // grow-only device scratch
     DevBuf pts, spts, keys[2], vals[2], inv, mark, child, pint, pleaf, range, counters, nodes, hist, stmp, bbox,
-        bpart, misc, loc, cnt_v, cnt_f, cnt_n, vol, cen, flags, offv, offf, offn, scan_tmp, list1, list2, stats, ctr;
-    DevBuf st_vert[3], st_tri64[3], st_code[3], st_fsize[3], st_fv[3];
-    DevBuf arena;  // per-wave cell arrays of the 16384-vertex pass
+        bpart, misc, loc, cnt_v, cnt_f, cnt_n, vol, cen, flags, offv, offf, offn, scan_tmp, stats, ctr;
+    DevBuf lists[vd::kTiers];  // lists[t]: cells handed on to tier t (t >= 1)
+    DevBuf st_vert[vd::kTiers], st_tri64[vd::kTiers], st_code[vd::kTiers], st_fsize[vd::kTiers], st_fv[vd::kTiers];
+    DevBuf arena;  // per-wave cell arrays of the last (16384-vertex) pass
     DevBuf bwd_facet, bwd_self, bwd_orphan;  // backward scratch
     // last build
     bool valid = false;
     int64_t n = 0;
     vd_sizes sizes{};
     const uint32_t* order = nullptr;
-    int tier_slots[3] = {0, 0, 0};
+    int tier_slots[vd::kTiers] = {};
     // profiling: events e[0..6] bracket the build phases, e[7..8] the write,
     // e[9..10] the backward
     hipEvent_t ev[11] = {};
@@ -55,6 +56,8 @@ struct vd_context {
 namespace {
 
 using vd::kTierCap;
+constexpr int kMiscWords = 16 + vd::kWorkRanges * vd::kTiers;
+static_assert(vd::kTiers <= 4 && vd::kWorkRanges == 8, "misc layout");
 
 vd_status ensure(DevBuf& b, size_t bytes) {
     if (bytes == 0) bytes = 16;
@@ -152,12 +155,13 @@ VD_API void vd_destroy(vd_context* c) {
     DevBuf* all[] = {&c->pts, &c->spts, &c->keys[0], &c->keys[1], &c->vals[0], &c->vals[1], &c->inv, &c->mark,
                      &c->child, &c->pint, &c->pleaf, &c->range, &c->counters, &c->nodes, &c->hist, &c->stmp,
                      &c->bbox, &c->bpart, &c->misc, &c->loc, &c->cnt_v, &c->cnt_f, &c->cnt_n, &c->vol, &c->cen,
-                     &c->flags, &c->offv, &c->offf, &c->offn, &c->scan_tmp, &c->list1, &c->list2, &c->stats,
+                     &c->flags, &c->offv, &c->offf, &c->offn, &c->scan_tmp, &c->stats,
                      &c->ctr, &c->arena, &c->bwd_facet, &c->bwd_self, &c->bwd_orphan};
     for (DevBuf* b : all) release(*b);
     if (c->ev_ready)
         for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
-    for (int t = 0; t < 3; ++t) {
+    for (int t = 0; t < vd::kTiers; ++t) {
+        release(c->lists[t]);
         release(c->st_vert[t]);
         release(c->st_tri64[t]);
         release(c->st_code[t]);
@@ -226,7 +230,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     VD_TRY(ensure(c->stmp, vd::scan_tmp_size((int64_t)vd::radix_hist_size(n)) * sizeof(uint64_t)));
     VD_TRY(ensure(c->bbox, 8 * sizeof(float)));
     VD_TRY(ensure(c->bpart, 1024 * 6 * sizeof(float)));
-    VD_TRY(ensure(c->misc, 16 * sizeof(uint32_t)));
+    VD_TRY(ensure(c->misc, kMiscWords * sizeof(uint32_t)));
     VD_TRY(ensure(c->loc, N * sizeof(uint32_t)));
     VD_TRY(ensure(c->cnt_v, N * sizeof(uint32_t)));
     VD_TRY(ensure(c->cnt_f, N * sizeof(uint32_t)));
@@ -238,17 +242,17 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     VD_TRY(ensure(c->offf, (N + 1) * sizeof(int64_t)));
     VD_TRY(ensure(c->offn, (N + 1) * sizeof(int64_t)));
     VD_TRY(ensure(c->scan_tmp, vd::scan_tmp_size(n) * sizeof(int64_t)));
-    VD_TRY(ensure(c->list1, N * sizeof(uint32_t)));
-    VD_TRY(ensure(c->list2, N * sizeof(uint32_t)));
+    for (int t = 1; t < vd::kTiers; ++t) VD_TRY(ensure(c->lists[t], N * sizeof(uint32_t)));
     VD_TRY(ensure(c->stats, vd::kStatCount * sizeof(unsigned long long)));
-    VD_TRY(ensure(c->ctr, 3 * vd::kCtrCount * sizeof(unsigned long long)));
+    VD_TRY(ensure(c->ctr, vd::kTiers * vd::kCtrCount * sizeof(unsigned long long)));
     VD_TRY(ensure_stage(c, 0, n));
 
-    // misc: [0] error bits, [1..3] work counters, [4] tier-1 list count, [5] tier-2 list count
+    // misc: [0] error bits, [4 + t] list count of tier t >= 1, [16 + 8 t ..] the
+    // kWorkRanges work counters of tier t
     uint32_t* misc = as<uint32_t>(c->misc);
     if (prof) VD_HIP(hipEventRecord(c->ev[0], s));
-    VD_HIP(hipMemsetAsync(misc, 0, 16 * sizeof(uint32_t), s));
-    if (o.counters) VD_HIP(hipMemsetAsync(c->ctr.p, 0, 3 * vd::kCtrCount * sizeof(unsigned long long), s));
+    VD_HIP(hipMemsetAsync(misc, 0, kMiscWords * sizeof(uint32_t), s));
+    if (o.counters) VD_HIP(hipMemsetAsync(c->ctr.p, 0, vd::kTiers * vd::kCtrCount * sizeof(unsigned long long), s));
     VD_HIP(hipMemsetAsync(c->stats.p, 0, vd::kStatCount * sizeof(unsigned long long), s));
     float4* pts = as<float4>(c->pts);
     float* dbbox = as<float>(c->bbox);
@@ -303,11 +307,11 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
 
     // tier 0: every cell
     a.tier = 0;
-    a.work_counter = misc + 1;
+    a.work_counter = misc + 16;
     a.list = nullptr;
     a.list_count = nullptr;
-    a.next_list = as<uint32_t>(c->list1);
-    a.next_count = misc + 4;
+    a.next_list = as<uint32_t>(c->lists[1]);
+    a.next_count = misc + 5;
     a.stage = stage_of(c, 0);
     c->tier_slots[0] = (int)n;
     if (prof) VD_HIP(hipEventRecord(c->ev[1], s));
@@ -319,24 +323,25 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     if (hmisc[0] & 1u) return fail(VD_ERR_INVALID_ARG, "vd_build: non-finite site coordinate or weight");
     if (hmisc[0] & 2u) return fail(VD_ERR_INVALID_ARG, "vd_build: degenerate bounding box");
     // larger tiers for the cells that outgrew the previous one
-    c->tier_slots[1] = c->tier_slots[2] = 0;
-    for (int tier = 1; tier < 3; ++tier) {
-        const uint32_t cnt = hmisc[3 + tier];
+    for (int tier = 1; tier < vd::kTiers; ++tier) c->tier_slots[tier] = 0;
+    for (int tier = 1; tier < vd::kTiers; ++tier) {
+        const uint32_t cnt = hmisc[4 + tier];
         c->tier_slots[tier] = (int)cnt;
         if (cnt == 0) break;
         VD_TRY(ensure_stage(c, tier, cnt));
         a.tier = tier;
-        a.work_counter = misc + 1 + tier;
-        a.list = as<uint32_t>(tier == 1 ? c->list1 : c->list2);
-        a.list_count = misc + 3 + tier;
-        a.next_list = tier == 1 ? as<uint32_t>(c->list2) : nullptr;
-        a.next_count = tier == 1 ? misc + 5 : nullptr;
+        a.work_counter = misc + 16 + vd::kWorkRanges * tier;
+        a.list = as<uint32_t>(c->lists[tier]);
+        a.list_count = misc + 4 + tier;
+        const bool last = tier + 1 == vd::kTiers;
+        a.next_list = last ? nullptr : as<uint32_t>(c->lists[tier + 1]);
+        a.next_count = last ? nullptr : misc + 5 + tier;
         a.stage = stage_of(c, tier);
         if (a.ctr) a.ctr = as<unsigned long long>(c->ctr) + tier * vd::kCtrCount;
         int waves = vd::clip_grid_waves(tier, c->num_cu);
         if ((int64_t)waves > (int64_t)cnt) waves = (int)cnt;
         void* arena = nullptr;
-        if (tier == 2) {
+        if (tier == 3) {
             VD_TRY(ensure(c->arena, (size_t)waves * vd::arena_bytes_per_wave()));
             arena = c->arena.p;
         }
@@ -375,7 +380,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     z.n_uncertain = (int64_t)st[vd::kStatUncertain];
     z.n_failed = (int64_t)st[vd::kStatFailed];
     z.n_fp64 = (int64_t)st[vd::kStatFP64];
-    z.n_huge = c->tier_slots[2];
+    z.n_huge = c->tier_slots[3];
     c->sizes = z;
     c->n = n;
     c->order = order;
@@ -384,7 +389,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     if (z.n_failed > 0)
         return fail(VD_ERR_CAPACITY, "vd_build: " + std::to_string(z.n_failed) +
                                          " cells exceeded the largest capacity (" +
-                                         std::to_string(kTierCap[2]) + " vertices); they are flagged");
+                                         std::to_string(kTierCap[vd::kTiers - 1]) + " vertices); they are flagged");
     return VD_OK;
 }
 
@@ -401,7 +406,7 @@ VD_API vd_status vd_write(vd_context* c, const vd_outputs* out, void* stream) {
     a.n = n;
     a.inv = as<uint32_t>(c->inv);
     a.loc = as<uint32_t>(c->loc);
-    for (int t = 0; t < 3; ++t) a.stage[t] = stage_of(c, t);
+    for (int t = 0; t < vd::kTiers; ++t) a.stage[t] = stage_of(c, t);
     a.cnt_v = as<uint32_t>(c->cnt_v);
     a.cnt_f = as<uint32_t>(c->cnt_f);
     a.cnt_n = as<uint32_t>(c->cnt_n);
@@ -475,7 +480,7 @@ VD_API vd_status vd_backward(vd_context* c, const float* g_vol, const float* g_c
     a.pts = as<float4>(c->spts);
     a.inv = as<uint32_t>(c->inv);
     a.loc = as<uint32_t>(c->loc);
-    for (int t = 0; t < 3; ++t) a.stage[t] = stage_of(c, t);
+    for (int t = 0; t < vd::kTiers; ++t) a.stage[t] = stage_of(c, t);
     a.cnt_v = as<uint32_t>(c->cnt_v);
     a.cnt_f = as<uint32_t>(c->cnt_f);
     a.cnt_n = as<uint32_t>(c->cnt_n);
@@ -501,9 +506,9 @@ VD_API vd_status vd_backward(vd_context* c, const float* g_vol, const float* g_c
 VD_API vd_status vd_get_counters(const vd_context* c, uint64_t* out, int32_t count) {
     if (!c || !out || count < 0) return fail(VD_ERR_INVALID_ARG, "vd_get_counters: bad argument");
     if (!c->valid || !c->counted) return fail(VD_ERR_STATE, "vd_get_counters: last build did not count");
-    unsigned long long h[3 * vd::kCtrCount];
+    unsigned long long h[vd::kTiers * vd::kCtrCount];
     VD_HIP(hipMemcpy(h, c->ctr.p, sizeof(h), hipMemcpyDeviceToHost));
-    for (int k = 0; k < count && k < 3 * vd::kCtrCount; ++k) out[k] = (uint64_t)h[k];
+    for (int k = 0; k < count && k < vd::kTiers * vd::kCtrCount; ++k) out[k] = (uint64_t)h[k];
     return VD_OK;
 }
 

@@ -44,7 +44,7 @@ struct CellRec {
 
 __device__ inline CellRec record_of(const BwdArgs& a, uint32_t k) {
     const uint32_t loc = a.loc[k], tier = loc >> 30;
-    const Stage st = tier == 0 ? a.stage[0] : (tier == 1 ? a.stage[1] : a.stage[2]);
+    const Stage st = tier == 0 ? a.stage[0] : (tier == 1 ? a.stage[1] : (tier == 2 ? a.stage[2] : a.stage[3]));
     const int64_t slot = loc & 0x3FFFFFFFu;
     const int64_t cap = st.cap;
     CellRec r;

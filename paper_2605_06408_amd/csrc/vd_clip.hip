@@ -27,11 +27,12 @@
 // each.
 //
 // Capacity tiers: 64 vertices (one slot; vertex state in registers, planes
-// and tables in LDS), 256 (four slots, same layout) and 16384 (256 slots; all
-// per-cell arrays in a per-wave global arena, slot loops bounded by the slots
-// in use).  A cell that outgrows a tier is handed to the next.  The paper's
-// own kernel keeps one cell per thread in global memory; that layout was made
-// for its GPUs and is not used.
+// and tables in LDS), 256 (four slots, same layout), 1024 (16 slots; every
+// per-cell array in LDS, one wave per workgroup) and 16384 (256 slots; every
+// per-cell array in a per-wave arena in global memory).  The last two run
+// their slot loops over the slots in use only.  A cell that outgrows a tier
+// is handed to the next.  The paper's own kernel keeps one cell per thread in
+// global memory; that layout was made for its GPUs and is not used.
 #include <type_traits>
 
 #include "vd_internal.h"
@@ -58,35 +59,71 @@ __device__ __forceinline__ uint32_t rdl(uint32_t v, int l) { return (uint32_t)__
 __device__ __forceinline__ int rdl(int v, int l) { return __builtin_amdgcn_readlane(v, l); }
 __device__ __forceinline__ float uni(float v) { return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v))); }
 __device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin_amdgcn_readfirstlane((int)v); }
+// Wave reductions by DPP lane moves (no LDS round trip): within quads
+// (quad_perm [1,0,3,2] and [2,3,0,1]), across half-rows and rows
+// (row_half_mirror, row_mirror), then row 0 into 1 and 2 into 3
+// (row_bcast:15) and rows 0-1 into 2-3 (row_bcast:31); lane 63 holds the
+// result, which is returned to every lane.  Lanes of rows a step does not
+// write keep `keep` (the operand's identity for sums, the value itself for
+// min and max).  All 64 lanes must be active.
+template <int kCtrl, int kRows>
+__device__ __forceinline__ int dpp(int keep, int v) {
+    return __builtin_amdgcn_update_dpp(keep, v, kCtrl, kRows, 0xF, false);
+}
+template <typename Op>
+__device__ __forceinline__ int wave_reduce_i(int v, int zero, bool idem, Op op) {
+    v = op(v, dpp<0xB1, 0xF>(idem ? v : zero, v));
+    v = op(v, dpp<0x4E, 0xF>(idem ? v : zero, v));
+    v = op(v, dpp<0x141, 0xF>(idem ? v : zero, v));
+    v = op(v, dpp<0x140, 0xF>(idem ? v : zero, v));
+    v = op(v, dpp<0x142, 0xA>(idem ? v : zero, v));
+    v = op(v, dpp<0x143, 0xC>(idem ? v : zero, v));
+    return __builtin_amdgcn_readlane(v, 63);
+}
 __device__ __forceinline__ float wmin(float v) {
-    for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o));
-    return uni(v);
+    return __int_as_float(wave_reduce_i(__float_as_int(v), 0, true, [](int a, int b) {
+        return __float_as_int(fminf(__int_as_float(a), __int_as_float(b)));
+    }));
 }
 __device__ __forceinline__ float wmax(float v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o));
-    return uni(v);
-}
-__device__ __forceinline__ double wsum64(double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return v;
+    return __int_as_float(wave_reduce_i(__float_as_int(v), 0, true, [](int a, int b) {
+        return __float_as_int(fmaxf(__int_as_float(a), __int_as_float(b)));
+    }));
 }
 __device__ __forceinline__ uint32_t wsum_u(uint32_t v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    return uni(v);
+    return (uint32_t)wave_reduce_i((int)v, 0, false, [](int a, int b) { return (int)((uint32_t)a + (uint32_t)b); });
+}
+template <int kCtrl, int kRows>
+__device__ __forceinline__ double dpp64(double v) {
+    const int lo = dpp<kCtrl, kRows>(0, __double2loint(v));
+    const int hi = dpp<kCtrl, kRows>(0, __double2hiint(v));
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double wsum64(double v) {
+    v += dpp64<0xB1, 0xF>(v);
+    v += dpp64<0x4E, 0xF>(v);
+    v += dpp64<0x141, 0xF>(v);
+    v += dpp64<0x140, 0xF>(v);
+    v += dpp64<0x142, 0xA>(v);
+    v += dpp64<0x143, 0xC>(v);
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    return __hiloint2double(hi, lo);
 }
 
 // Sizes and index packings of a tier.  Three vertex or plane indices are
-// packed into one word: 10 bits each in 32-bit words for the register tiers,
-// 15 bits each in 64-bit words for the arena tier.
+// packed into one word: 10 bits each in 32-bit words up to 1024 vertices,
+// 15 bits each in 64-bit words above.
 template <int VPL>
 struct Tier {
     static constexpr int CAP = 64 * VPL;
-    static constexpr bool kReg = VPL <= 16;  // vertex state in registers, slot loops unrolled
-    static constexpr int kB = kReg ? 10 : 15;
-    using W = typename std::conditional<kReg, uint32_t, uint64_t>::type;
+    static constexpr bool kReg = VPL <= 4;  // vertex state in registers, slot loops unrolled
+    static constexpr bool kNarrow = CAP <= 1024;
+    static constexpr int kB = kNarrow ? 10 : 15;
+    using W = typename std::conditional<kNarrow, uint32_t, uint64_t>::type;
     static constexpr W kMask = (W(1) << kB) - 1;
     // new-vertex table entries: serial tag above the vertex index
-    static constexpr int kTagShift = kReg ? 12 : 16;
+    static constexpr int kTagShift = kNarrow ? 12 : 16;
     static constexpr uint32_t kTagMax = (1u << (32 - kTagShift)) - 2u;
     __device__ __forceinline__ static uint32_t fld(W w, int k) { return (uint32_t)((w >> (kB * k)) & kMask); }
     __device__ __forceinline__ static W setfld(W w, int k, uint32_t v) {
@@ -98,9 +135,9 @@ struct Tier {
 };
 
 // Orders this wave's accesses to its per-cell arrays, so that what one lane
-// wrote before is seen by every lane after: LDS for the register tiers (one
-// wave, no workgroup barrier needed), global memory for the arena tier (one
-// wave per workgroup).
+// wrote before is seen by every lane after: LDS (one wave, no workgroup
+// barrier needed) or, for the arena tier, global memory (one wave per
+// workgroup).
 template <bool kLds>
 __device__ __forceinline__ void wave_sync() {
     if constexpr (kLds) {
@@ -127,8 +164,9 @@ struct Col {
     }
 };
 
-// Arena-tier state that the register tiers keep in registers (index
-// slot * 64 + lane for per-lane values, slot for wave-uniform masks).
+// Per-cell state that the register tiers keep in registers and the larger
+// tiers in LDS or the arena (index slot * 64 + lane for per-lane values, slot
+// for wave-uniform masks).
 template <int VPL, bool kArena = !Tier<VPL>::kReg>
 struct ArenaState {};
 template <int VPL>
@@ -170,7 +208,10 @@ struct P64 {
     double a0, a1, a2, b;
 };
 
-template <int VPL>
+// kLds: the per-cell arrays are in LDS (else in global memory).  kCount:
+// count work units and cycles (a separate instantiation, so the timed
+// kernels carry no counting code).
+template <int VPL, bool kLds, bool kCount>
 struct Cell {
     using T = Tier<VPL>;
     using W = typename T::W;
@@ -204,15 +245,14 @@ struct Cell {
     Lane<float> qk;
     int qn;
     // work counters (uniform), accumulated over all cells of this wave
-    uint64_t ctr[kCtrCount];
-    bool counting;
+    uint64_t ctr[kCount ? kCtrCount : 1];
+    static constexpr bool counting = kCount;
 
     // the first clip clears the new-vertex tables (the tag counter starts
     // at its wrap-around value)
     __device__ Cell(WaveMem<VPL>& m, const ClipArgs& a) : M(m), A(a), ln(lane_id()), serial(T::kTagMax - 1) {
-        counting = a.ctr != nullptr;
 #pragma unroll
-        for (int c = 0; c < kCtrCount; ++c) ctr[c] = 0;
+        for (int c = 0; c < (kCount ? kCtrCount : 1); ++c) ctr[c] = 0;
         if constexpr (!kReg) {
             y0.m = M.y0 + ln; y1.m = M.y1 + ln; y2.m = M.y2 + ln; ev.m = M.ev + ln;
             vt.m = M.vt + ln; va.m = M.va + ln;
@@ -222,9 +262,17 @@ struct Cell {
         vhi = CAP;
     }
     __device__ __forceinline__ void count(int c, uint64_t v) {
-        if (counting) ctr[c] += v;
+        if constexpr (kCount) ctr[c] += v;
     }
-    __device__ __forceinline__ void sync() { wave_sync<kReg>(); }
+    // elapsed shader clock of this wave, accumulated per phase when counting
+    __device__ __forceinline__ uint64_t tic() const {
+        if constexpr (kCount) return (uint64_t)clock64();
+        else return 0ull;
+    }
+    __device__ __forceinline__ void toc(int c, uint64_t t0) {
+        if constexpr (kCount) ctr[c] += (uint64_t)clock64() - t0;
+    }
+    __device__ __forceinline__ void sync() { wave_sync<kLds>(); }
     // slots that may hold vertices (all of them in the register tiers)
     __device__ __forceinline__ int nsv() const { return kReg ? VPL : ((vhi + 63) >> 6); }
     __device__ __forceinline__ uint64_t nalive() {
@@ -330,7 +378,7 @@ struct Cell {
     // |v - p_j|^2 - w_j < |v|^2 - w_i, and |v - p_j|^2 >= dist(v, box)^2.
     // Returns true if some vertex might be cut (the box cannot be skipped).
     __device__ bool ball_hit(float lx, float ly, float lz, float hx, float hy, float hz, float wm) {
-        if (counting) count(kCtrBall, nalive());
+        if constexpr (kCount) count(kCtrBall, nalive());
         bool hit = false;
         const int ns = nsv();
 #pragma unroll
@@ -413,7 +461,7 @@ struct Cell {
     __device__ void classify(float ax, float ay, float az, float b, float sbh, int32_t hcode, float4 hsite,
                              int mode, Wave<uint64_t>& R) {
         const float an1 = fabsf(ax) + fabsf(ay) + fabsf(az);
-        if (counting && mode != 2) count(kCtrClassify, nalive());
+        if (kCount && mode != 2) count(kCtrClassify, nalive());
         const int ns = nsv();
         uint64_t amb_any = 0;
         Lane<uint8_t> amb;
@@ -435,6 +483,12 @@ struct Cell {
         }
         if ((mode == 1 || mode == 3) && amb_any) {
             flags |= kFlagFP64;
+            if constexpr (kCount) {
+                uint64_t na = 0;
+#pragma unroll
+                for (int s = 0; s < (kReg ? VPL : ns); ++s) na += (uint64_t)popc(ballot(amb[s] != 0));
+                count(kCtrFP64, na);
+            }
             P64 h = plane64(hcode, hsite);
 #pragma unroll
             for (int s = 0; s < (kReg ? VPL : ns); ++s) {
@@ -941,7 +995,9 @@ struct Cell {
             float hx = rdl(ax, L), hy = rdl(ay, L), hz = rdl(az, L), hb = rdl(b, L);
             float sb = 0.5f * (rdl(a2, L) + fabsf(rdl(dw, L)));
             float4 hs = make_float4(rdl(q.x, L), rdl(q.y, L), rdl(q.z, L), rdl(q.w, L));
+            const uint64_t t0 = tic();
             int r = clip(hx, hy, hz, hb, sb, (int32_t)(first + (uint32_t)L), hs);
+            toc(kCtrCycClip, t0);
             if (r == kEmptied || r == kOverflow || r == kRestart) return r;
             if (r == kChanged) {
                 update_bounds();
@@ -1000,7 +1056,9 @@ struct Cell {
                 cur = rdl(ref, near);
             }
             if (have) {
+                const uint64_t t0 = tic();
                 int r = leaf(cur);
+                toc(kCtrCycLeaf, t0);
                 if (r != kNone) return r;
             }
             have = false;
@@ -1240,16 +1298,39 @@ struct Cell {
 };
 
 // The per-wave work loop shared by every tier.
-template <int VPL>
+template <int VPL, bool kLds, bool kCount>
 __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A) {
-    Cell<VPL> C(M, A);
+    Cell<VPL, kLds, kCount> C(M, A);
     const uint32_t count = A.list ? *A.list_count : (uint32_t)A.n;
     unsigned long long st_empty = 0, st_large = 0, st_unc = 0, st_fail = 0, st_fp64 = 0;
+    // Cells are split into kWorkRanges contiguous (Morton-ordered) ranges, one
+    // per XCD: the waves of workgroup b take chunks of their own range b % 8
+    // first, so neighbouring cells (which walk the same nodes and sites) share
+    // one L2, then help the other ranges.  Chunks cut the atomics per cell.
+    uint32_t r = blockIdx.x % kWorkRanges;
+    int tried = 0;
+    uint32_t cur = 0, end = 0;
     for (;;) {
-        uint32_t c = 0;
-        if (C.ln == 0) c = atomicAdd(A.work_counter, 1u);
-        c = uni(c);
-        if (c >= count) break;
+        if (cur >= end) {
+            bool got = false;
+            while (tried < kWorkRanges) {
+                const uint32_t lo = (uint32_t)((uint64_t)count * r / kWorkRanges);
+                const uint32_t hi = (uint32_t)((uint64_t)count * (r + 1) / kWorkRanges);
+                uint32_t c0 = 0;
+                if (C.ln == 0) c0 = atomicAdd(&A.work_counter[r], (uint32_t)kWorkChunk);
+                c0 = uni(c0);
+                if (c0 < hi - lo) {
+                    cur = lo + c0;
+                    end = min(hi, cur + (uint32_t)kWorkChunk);
+                    got = true;
+                    break;
+                }
+                r = (r + 1) % kWorkRanges;
+                ++tried;
+            }
+            if (!got) break;
+        }
+        const uint32_t c = cur++;
         const uint32_t k = A.list ? A.list[c] : c;
         const uint32_t slot = A.list ? c : k;
         const uint32_t orig = A.order[k];
@@ -1266,7 +1347,9 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A) {
             }
             if (attempt > 0) C.flags |= kFlagFP64;
             if (A.tier > 0) C.flags |= kFlagLarge;
+            const uint64_t t0 = C.tic();
             int r = C.traverse();
+            C.toc(kCtrCycTraverse, t0);
             if (r == kRestart) {
                 C.robust = C.robust + 1;
                 continue;
@@ -1287,7 +1370,12 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A) {
                 C.write_empty(orig, 0);
                 ++st_empty;
                 done = true;
-            } else if (C.finalize(slot, orig)) {
+            } else if ([&] {
+                           const uint64_t t1 = C.tic();
+                           const bool ok = C.finalize(slot, orig);
+                           C.toc(kCtrCycFinal, t1);
+                           return ok;
+                       }()) {
                 done = true;
             } else if (C.robust < 2) {
                 C.robust = C.robust + 1;
@@ -1312,7 +1400,7 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A) {
         st_fp64 += (C.flags & kFlagFP64) ? 1 : 0;
     }
     if (C.ln == 0) {
-        if (C.counting)
+        if constexpr (kCount)
             for (int c = 0; c < kCtrCount; ++c)
                 if (C.ctr[c]) atomicAdd(&A.ctr[c], (unsigned long long)C.ctr[c]);
         if (st_empty) atomicAdd(&A.stats[kStatEmpty], st_empty);
@@ -1323,20 +1411,26 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A) {
     }
 }
 
-// Register tiers: per-cell arrays in LDS, several independent waves per block.
-template <int VPL, int WAVES>
-__global__ __launch_bounds__(64 * WAVES) void k_clip(ClipArgs A) {
+// LDS tiers: per-cell arrays in LDS, WAVES independent waves per block.
+// The 64-vertex pass is bound by the latency of its dependent node and site
+// loads: it is held to 128 VGPRs for 4 waves per SIMD (a few spills cost
+// less than the lost occupancy).
+template <int VPL, int WAVES, bool kCount>
+__global__ __launch_bounds__(64 * WAVES, VPL == 1 ? 4 : 1) void k_clip(ClipArgs A) {
     __shared__ WaveMem<VPL> mem[WAVES];
-    run_cells<VPL>(mem[threadIdx.x >> 6], A);
+    run_cells<VPL, true, kCount>(mem[threadIdx.x >> 6], A);
 }
 
 // Arena tier: one wave per block, its per-cell arrays in arena[blockIdx.x].
-constexpr int kArenaVPL = kTierCap[2] / 64;
+constexpr int kArenaVPL = kTierCap[3] / 64;
+template <bool kCount>
 __global__ __launch_bounds__(64) void k_clip_arena(ClipArgs A, WaveMem<kArenaVPL>* arena) {
-    run_cells<kArenaVPL>(arena[blockIdx.x], A);
+    run_cells<kArenaVPL, false, kCount>(arena[blockIdx.x], A);
 }
 
-static_assert(kTierCap[0] == 64 && kTierCap[1] == 256, "register tiers are instantiated for 64 and 256 vertices");
+static_assert(kTierCap[0] == 64 && kTierCap[1] == 256 && kTierCap[2] == 1024,
+              "the LDS tiers are instantiated for 64, 256 and 1024 vertices");
+static_assert(sizeof(WaveMem<16>) <= 160 * 1024, "the 1024-vertex tier must fit the LDS of one CU");
 static_assert(Tier<kArenaVPL>::CAP <= (1 << Tier<kArenaVPL>::kB) && Tier<kArenaVPL>::CAP <= (1 << 16),
               "arena-tier indices must fit their packings and the 16-bit staged facet lists");
 
@@ -1348,11 +1442,13 @@ int clip_grid_waves(int tier, int num_cu) {
     int per_cu = 0;
     hipError_t e = hipSuccess;
     if (tier == 0) {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip<1, 4>, 256, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip<1, 4, false>, 256, 0);
         per_cu *= 4;
     } else if (tier == 1) {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip<4, 2>, 128, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip<4, 2, false>, 128, 0);
         per_cu *= 2;
+    } else if (tier == 2) {
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip<16, 1, false>, 64, 0);
     } else {
         per_cu = 2;  // arena waves: bounded by arena memory, not by occupancy
     }
@@ -1360,24 +1456,29 @@ int clip_grid_waves(int tier, int num_cu) {
     return per_cu * num_cu;
 }
 
-hipError_t launch_clip(const ClipArgs& a, int grid_waves, void* arena, hipStream_t s) {
+template <bool kCount>
+void launch_tier(const ClipArgs& a, int grid_waves, void* arena, hipStream_t s) {
     switch (a.tier) {
-        case 0: {
-            int blocks = (grid_waves + 3) / 4;
-            hipLaunchKernelGGL((k_clip<1, 4>), dim3(blocks), dim3(256), 0, s, a);
+        case 0:
+            hipLaunchKernelGGL((k_clip<1, 4, kCount>), dim3((grid_waves + 3) / 4), dim3(256), 0, s, a);
             break;
-        }
-        case 1: {
-            int blocks = (grid_waves + 1) / 2;
-            hipLaunchKernelGGL((k_clip<4, 2>), dim3(blocks), dim3(128), 0, s, a);
+        case 1:
+            hipLaunchKernelGGL((k_clip<4, 2, kCount>), dim3((grid_waves + 1) / 2), dim3(128), 0, s, a);
             break;
-        }
+        case 2:
+            hipLaunchKernelGGL((k_clip<16, 1, kCount>), dim3(grid_waves), dim3(64), 0, s, a);
+            break;
         default:
-            if (!arena) return hipErrorInvalidValue;
-            hipLaunchKernelGGL(k_clip_arena, dim3(grid_waves), dim3(64), 0, s, a,
+            hipLaunchKernelGGL((k_clip_arena<kCount>), dim3(grid_waves), dim3(64), 0, s, a,
                                static_cast<WaveMem<kArenaVPL>*>(arena));
             break;
     }
+}
+
+hipError_t launch_clip(const ClipArgs& a, int grid_waves, void* arena, hipStream_t s) {
+    if (a.tier >= 3 && !arena) return hipErrorInvalidValue;
+    if (a.ctr) launch_tier<true>(a, grid_waves, arena, s);
+    else launch_tier<false>(a, grid_waves, arena, s);
     return hipGetLastError();
 }
 

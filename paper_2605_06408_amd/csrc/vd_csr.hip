@@ -127,7 +127,8 @@ __global__ __launch_bounds__(256) void k_write(WriteArgs a) {
     for (int64_t i = wave; i < a.n; i += nwaves) {
         const uint32_t k = a.inv[i];
         const uint32_t loc = a.loc[k];
-        const Stage& st = a.stage[loc >> 30];
+        const uint32_t tier = loc >> 30;
+        const Stage st = tier == 0 ? a.stage[0] : (tier == 1 ? a.stage[1] : (tier == 2 ? a.stage[2] : a.stage[3]));
         const int64_t slot = loc & 0x3FFFFFFFu;
         const int cap = st.cap;
         const float4* V = st.vert + slot * cap;

@@ -12,8 +12,13 @@ namespace vd {
 constexpr int kMaxLeaf = 64;                 // leaf refs store count-1 in 6 bits
 constexpr int64_t kMaxSites = int64_t(1) << 25;  // leaf refs store `first` in 25 bits
 constexpr int kDefaultLeaf = 16;
+// Work distribution of the clip kernels: one contiguous range of cells per
+// XCD (workgroup b runs on XCD b % 8), taken kWorkChunk cells at a time.
+constexpr int kWorkRanges = 8;
+constexpr int kWorkChunk = 4;
 // Vertex (= plane) capacity of a cell in each clipping pass.
-constexpr int kTierCap[3] = {64, 256, 16384};
+constexpr int kTiers = 4;
+constexpr int kTierCap[kTiers] = {64, 256, 1024, 16384};
 
 // ---------------------------------------------------------------- BVH
 
@@ -72,7 +77,7 @@ constexpr uint32_t kFlagEmpty = 1u, kFlagFP64 = 2u, kFlagLarge = 4u, kFlagUncert
 enum StatIndex { kStatEmpty = 0, kStatLarge, kStatUncertain, kStatFailed, kStatFP64, kStatCount };
 // Work counters (mirror VD_CTR_* in vd.h).
 enum CtrIndex { kCtrClassify = 0, kCtrNewVertex, kCtrNode, kCtrSite, kCtrFinal, kCtrClip, kCtrEffective, kCtrLeaf,
-                kCtrBall, kCtrCount };
+                kCtrBall, kCtrFP64, kCtrCycTraverse, kCtrCycLeaf, kCtrCycClip, kCtrCycFinal, kCtrCount };
 
 struct ClipArgs {
     const float4* pts;        // sites in Morton order: x, y, z, w (w = -inf: coincident loser)
@@ -85,8 +90,9 @@ struct ClipArgs {
     int culling;              // 1 directional, 2 isotropic
     int traversal;            // 1 best-first, 2 depth-first
     int precision;            // 1 fp32, 2 mixed
-    int tier;                 // 0, 1, 2 (capacity kTierCap[tier])
-    // work: cells c in [0, count) are list[c] (or c itself when list == null)
+    int tier;                 // 0..3 (capacity kTierCap[tier])
+    // work: cells c in [0, count) are list[c] (or c itself when list == null),
+    // split into kWorkRanges contiguous ranges with one counter each (zeroed)
     uint32_t* work_counter;
     const uint32_t* list;
     const uint32_t* list_count;   // device count (list != null), else count = n
@@ -108,7 +114,7 @@ struct WriteArgs {
     int64_t n;
     const uint32_t* inv;      // original index -> Morton position
     const uint32_t* loc;
-    Stage stage[3];
+    Stage stage[kTiers];
     const uint32_t* cnt_v;
     const uint32_t* cnt_f;
     const uint32_t* cnt_n;
@@ -129,7 +135,7 @@ struct BwdArgs {
     const float4* pts;        // sites in Morton order: x, y, z, w
     const uint32_t* inv;      // original index -> Morton position
     const uint32_t* loc;      // staged record of each cell, by Morton position
-    Stage stage[3];
+    Stage stage[kTiers];
     const uint32_t* cnt_v;    // by original index
     const uint32_t* cnt_f;
     const uint32_t* cnt_n;
@@ -181,7 +187,7 @@ hipError_t scan_counts(const uint32_t* in, int64_t n, int64_t* out, int64_t* tmp
 hipError_t scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* tmp, hipStream_t s);
 
 // Waves to launch for a clipping pass, and the per-wave arena the last pass
-// (tier 2) needs: launch_clip(tier 2) takes grid_waves * arena_bytes_per_wave().
+// (tier 3) needs: launch_clip(tier 3) takes grid_waves * arena_bytes_per_wave().
 int clip_grid_waves(int tier, int num_cu);
 size_t arena_bytes_per_wave();
 hipError_t launch_clip(const ClipArgs& a, int grid_waves, void* arena, hipStream_t s);
