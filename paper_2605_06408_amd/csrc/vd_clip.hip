@@ -343,17 +343,42 @@ struct Cell {
         return true;
     }
 
+    // Slots are visited kBatch at a time: in the LDS and arena tiers every
+    // load of a batch is issued before any is used (one wait per batch, not
+    // per slot).  Slots at or above ns read as dead (the loads stay in
+    // bounds: VPL is a multiple of kBatch).
+    static constexpr int kBatch = kReg ? VPL : 4;
+    struct VBatch {
+        float a[kBatch], b[kBatch], c[kBatch];
+        uint64_t al[kBatch];
+    };
+    __device__ __forceinline__ void load_batch(int s0, int ns, VBatch& v) {
+#pragma unroll
+        for (int k = 0; k < kBatch; ++k) {
+            const int s = s0 + k;
+            v.a[k] = y0[s];
+            v.b[k] = y1[s];
+            v.c[k] = y2[s];
+            const uint64_t al = alive[s];
+            v.al[k] = s < ns ? al : 0ull;
+        }
+    }
+
     __device__ void update_bounds() {
         float mn0 = INFINITY, mn1 = INFINITY, mn2 = INFINITY, mx0 = -INFINITY, mx1 = -INFINITY, mx2 = -INFINITY,
               r2 = 0.f;
         const int ns = nsv();
+        for (int s0 = 0; s0 < (kReg ? VPL : ns); s0 += kBatch) {
+            VBatch v;
+            load_batch(s0, ns, v);
 #pragma unroll
-        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
-            if ((alive[s] >> ln) & 1) {
-                const float a = y0[s], b = y1[s], c = y2[s];
-                mn0 = fminf(mn0, a); mn1 = fminf(mn1, b); mn2 = fminf(mn2, c);
-                mx0 = fmaxf(mx0, a); mx1 = fmaxf(mx1, b); mx2 = fmaxf(mx2, c);
-                r2 = fmaxf(r2, fmaf(a, a, fmaf(b, b, c * c)));
+            for (int k = 0; k < kBatch; ++k) {
+                if ((v.al[k] >> ln) & 1) {
+                    const float a = v.a[k], b = v.b[k], c = v.c[k];
+                    mn0 = fminf(mn0, a); mn1 = fminf(mn1, b); mn2 = fminf(mn2, c);
+                    mx0 = fmaxf(mx0, a); mx1 = fmaxf(mx1, b); mx2 = fmaxf(mx2, c);
+                    r2 = fmaxf(r2, fmaf(a, a, fmaf(b, b, c * c)));
+                }
             }
         }
         float l0 = wmin(mn0), l1 = wmin(mn1), l2 = wmin(mn2);
@@ -381,17 +406,21 @@ struct Cell {
         if constexpr (kCount) count(kCtrBall, nalive());
         bool hit = false;
         const int ns = nsv();
+        for (int s0 = 0; s0 < (kReg ? VPL : ns); s0 += kBatch) {
+            VBatch v;
+            load_batch(s0, ns, v);
 #pragma unroll
-        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
-            if ((alive[s] >> ln) & 1) {
-                const float a = y0[s], b = y1[s], c = y2[s];
-                float dx = fmaxf(fmaxf(lx - a, a - hx), 0.f);
-                float dy = fmaxf(fmaxf(ly - b, b - hy), 0.f);
-                float dz = fmaxf(fmaxf(lz - c, c - hz), 0.f);
-                float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                float r2 = fmaf(a, a, fmaf(b, b, c * c));
-                float lhs = d2 - wm, rhs = r2 - pw;
-                hit |= lhs - rhs <= 16.f * kU * (d2 + r2 + fabsf(wm) + fabsf(pw));
+            for (int k = 0; k < kBatch; ++k) {
+                if ((v.al[k] >> ln) & 1) {
+                    const float a = v.a[k], b = v.b[k], c = v.c[k];
+                    float dx = fmaxf(fmaxf(lx - a, a - hx), 0.f);
+                    float dy = fmaxf(fmaxf(ly - b, b - hy), 0.f);
+                    float dz = fmaxf(fmaxf(lz - c, c - hz), 0.f);
+                    float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    float r2 = fmaf(a, a, fmaf(b, b, c * c));
+                    float lhs = d2 - wm, rhs = r2 - pw;
+                    hit |= lhs - rhs <= 16.f * kU * (d2 + r2 + fabsf(wm) + fabsf(pw));
+                }
             }
         }
         return ballot(hit) != 0;
@@ -459,27 +488,43 @@ struct Cell {
     // mode 0: plain FP32 signs; 1: doubtful signs re-evaluated in FP64;
     // 2: doubtful signs taken as inside; 3: every sign evaluated in FP64.
     __device__ void classify(float ax, float ay, float az, float b, float sbh, int32_t hcode, float4 hsite,
-                             int mode, Wave<uint64_t>& R) {
+                             int mode, Wave<uint64_t>& R, bool* any_out, bool* all_out) {
         const float an1 = fabsf(ax) + fabsf(ay) + fabsf(az);
         if (kCount && mode != 2) count(kCtrClassify, nalive());
         const int ns = nsv();
         uint64_t amb_any = 0;
+        bool anyo = false, allo = true;
         Lane<uint8_t> amb;
         if constexpr (!kReg) amb.m = M.amb + ln;
-#pragma unroll
-        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
-            const float sv = fmaf(ax, y0[s], fmaf(ay, y1[s], fmaf(az, y2[s], -b)));
-            const bool al = (alive[s] >> ln) & 1;
-            bool o = al && sv > 0.f;
-            bool am = false;
+        for (int s0 = 0; s0 < (kReg ? VPL : ns); s0 += kBatch) {
+            VBatch v;
+            load_batch(s0, ns, v);
+            float e[kBatch];
             if (mode != 0) {
-                float beta = 64.f * kU * (an1 * ev[s] + sbh);
-                am = al && (mode == 3 || fabsf(sv) <= beta);
-                if (am && mode == 2) o = false;
+#pragma unroll
+                for (int k = 0; k < kBatch; ++k) e[k] = ev[s0 + k];
             }
-            amb[s] = am;
-            R[s] = ballot(o);
-            amb_any |= ballot(am);
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                const int s = s0 + k;
+                const float sv = fmaf(ax, v.a[k], fmaf(ay, v.b[k], fmaf(az, v.c[k], -b)));
+                const bool al = (v.al[k] >> ln) & 1;
+                bool o = al && sv > 0.f;
+                bool am = false;
+                if (mode != 0) {
+                    float beta = 64.f * kU * (an1 * e[k] + sbh);
+                    am = al && (mode == 3 || fabsf(sv) <= beta);
+                    if (am && mode == 2) o = false;
+                }
+                const uint64_t r = ballot(o);
+                if (s < ns) {
+                    amb[s] = am;
+                    R[s] = r;
+                }
+                amb_any |= ballot(am);
+                anyo |= r != 0;
+                allo &= r == v.al[k];
+            }
         }
         if ((mode == 1 || mode == 3) && amb_any) {
             flags |= kFlagFP64;
@@ -490,6 +535,8 @@ struct Cell {
                 count(kCtrFP64, na);
             }
             P64 h = plane64(hcode, hsite);
+            anyo = false;
+            allo = true;
 #pragma unroll
             for (int s = 0; s < (kReg ? VPL : ns); ++s) {
                 bool o = (R[s] >> ln) & 1;
@@ -499,24 +546,23 @@ struct Cell {
                     o = sg > 0;
                     unsure = sg == 0;
                 }
-                R[s] = ballot(o);
+                const uint64_t r = ballot(o);
+                R[s] = r;
+                anyo |= r != 0;
+                allo &= r == alive[s];
                 if (ballot(unsure)) flags |= kFlagUncertain;
             }
         }
+        *any_out = anyo;
+        *all_out = allo;
     }
 
     // Tries the clip with the given outside masks; on an inconsistent
     // boundary sets *consistent = false and leaves the cell untouched.
-    __device__ int apply(Wave<uint64_t>& R, float ax, float ay, float az, float b, float sbh, int32_t hcode,
-                         float4 hsite, bool* consistent) {
+    __device__ int apply(Wave<uint64_t>& R, bool any, bool all, float ax, float ay, float az, float b, float sbh,
+                         int32_t hcode, float4 hsite, bool* consistent) {
         *consistent = true;
         const int ns = nsv();
-        bool any = false, all = true;
-#pragma unroll
-        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
-            any |= R[s] != 0;
-            all &= R[s] == alive[s];
-        }
         if (!any) return kNone;
         if (all) return kEmptied;
         if (np >= CAP) {
@@ -729,14 +775,15 @@ struct Cell {
         Wave<uint64_t> R;
         if constexpr (!kReg) R.m = M.R;
         count(kCtrClip, 1);
-        classify(ax, ay, az, b, sbh, hcode, hsite, robust == 0 ? 0 : (robust == 1 ? 1 : 3), R);
+        bool any, all;
+        classify(ax, ay, az, b, sbh, hcode, hsite, robust == 0 ? 0 : (robust == 1 ? 1 : 3), R, &any, &all);
         bool ok;
-        int r = apply(R, ax, ay, az, b, sbh, hcode, hsite, &ok);
+        int r = apply(R, any, all, ax, ay, az, b, sbh, hcode, hsite, &ok);
         if (ok) return r;
         if (robust < 2) return kRestart;
         flags |= kFlagUncertain;
-        classify(ax, ay, az, b, sbh, hcode, hsite, 2, R);
-        r = apply(R, ax, ay, az, b, sbh, hcode, hsite, &ok);
+        classify(ax, ay, az, b, sbh, hcode, hsite, 2, R, &any, &all);
+        r = apply(R, any, all, ax, ay, az, b, sbh, hcode, hsite, &ok);
         return ok ? r : kNone;
     }
 
