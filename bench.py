@@ -44,12 +44,12 @@ PEAK_HBM_GBS = 8000.0
 # HBM traffic of the 64-vertex clip kernel per launch, from two rocprofv3 --pmc
 # runs (FETCH_SIZE, WRITE_SIZE; KiB per dispatch) of bench.py on the named
 # workload, each scaled by what the same counter reads for a plain 256 MiB
-# device copy in the same run (FETCH_SIZE 131088.7 KiB -> x2.0, WRITE_SIZE
+# device copy in the same run (FETCH_SIZE 131088.4 KiB -> x2.0, WRITE_SIZE
 # 262144.0 KiB -> x1.0).  Valid only while the kernel source is unchanged.
 TRAFFIC_MEASURED = {
-    "sources_sha1": {"paper_2605_06408_amd/csrc/vd_clip.hip": "734cd0f1444d1abcfc30103b2f247039312bb772",
-                     "paper_2605_06408_amd/csrc/vd_internal.h": "2e209136d06e205eb0832a129b55eeb2a51a943f"},
-    "workload": "clustered_1m", "fetch_kib": 139334.6, "write_kib": 908202.3, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sources_sha1": {"paper_2605_06408_amd/csrc/vd_clip.hip": "4553654c1b50261873ccbdceaa132c8665fd17a1",
+                     "paper_2605_06408_amd/csrc/vd_internal.h": "1eddb2b1e39deae065a11e77d6a29d4e7ebcf703"},
+    "workload": "clustered_1m", "fetch_kib": 184965.0, "write_kib": 1787429.3, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
@@ -252,7 +252,7 @@ def main():
     traffic = measured_traffic(args.config)
     roofline = {"bound": "alu", "achieved": achieved, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / PEAK_FP32_TFLOPS, "traffic": traffic,
-                "kernel": "k_clip<1,4> (64-vertex tier)", "kernel_ms": clip_s * 1000.0,
+                "kernel": "k_clip<1,4,false> (64-vertex pass)", "kernel_ms": clip_s * 1000.0,
                 "flops_per_launch": flops}
 
     out = {
