@@ -885,7 +885,23 @@ struct Cell {
         float d = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
         float dw = pw - c.wmax;
         float lb, err;
-        if (dw >= 0.f) {
+        if (dw > 0.f && A.culling == 3) {
+            // every site j in the box has b_j / |a_j| >= f(|a_j|) with
+            // f(t) = t/2 + dw/(2t), and |a_j| lies between the box's nearest
+            // and farthest distances: the bound is f at sqrt(dw) clamped to
+            // that range (the paper's bound keeps only dw < 0 and is d/2 here)
+            const float fx = fmaxf(fabsf(blx), fabsf(bhx)), fy = fmaxf(fabsf(bly), fabsf(bhy)),
+                        fz = fmaxf(fabsf(blz), fabsf(bhz));
+            const float dfar = sqrtf(fmaf(fx, fx, fmaf(fy, fy, fz * fz)));
+            const float dc = fminf(fmaxf(sqrtf(dw), d), dfar);
+            if (dc > 0.f) {
+                lb = 0.5f * dc + 0.5f * dw / dc;
+                err = lb;
+            } else {
+                lb = 0.5f * d;
+                err = 0.5f * d;
+            }
+        } else if (dw >= 0.f) {
             lb = 0.5f * d;
             err = 0.5f * d;
         } else if (d > 0.f) {
