@@ -1475,11 +1475,11 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A) {
 }
 
 // LDS tiers: per-cell arrays in LDS, WAVES independent waves per block.
-// The 64-vertex pass is bound by the latency of its dependent node and site
-// loads: it is held to 128 VGPRs for 4 waves per SIMD (a few spills cost
-// less than the lost occupancy).
+// Register budgets: the 64-vertex pass is held to 128 registers for 4 waves
+// per SIMD, the 256-vertex pass to 256 for 2 (a few spills cost less than
+// the lost occupancy: both passes issue VALU work back to back).
 template <int VPL, int WAVES, bool kCount>
-__global__ __launch_bounds__(64 * WAVES, VPL == 1 ? 4 : 1) void k_clip(ClipArgs A) {
+__global__ __launch_bounds__(64 * WAVES, VPL == 1 ? 4 : (VPL == 4 ? 2 : 1)) void k_clip(ClipArgs A) {
     __shared__ WaveMem<VPL> mem[WAVES];
     run_cells<VPL, true, kCount>(mem[threadIdx.x >> 6], A);
 }
