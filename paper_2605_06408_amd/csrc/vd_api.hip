@@ -37,7 +37,7 @@ struct vd_context {
         bpart, misc, loc, cnt_v, cnt_f, cnt_n, vol, cen, flags, offv, offf, offn, scan_tmp, stats, ctr;
     DevBuf lists[vd::kTiers];  // lists[t]: cells handed on to tier t (t >= 1)
     DevBuf st_vert[vd::kTiers], st_tri64[vd::kTiers], st_code[vd::kTiers], st_fsize[vd::kTiers], st_fv[vd::kTiers];
-    DevBuf arena;  // per-wave cell arrays of the last (16384-vertex) pass
+    DevBuf arena;  // per-worker cell arrays of the last (16384-vertex) pass
     DevBuf bwd_facet, bwd_self, bwd_orphan;  // backward scratch
     // last build
     bool valid = false;
@@ -315,7 +315,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     a.stage = stage_of(c, 0);
     c->tier_slots[0] = (int)n;
     if (prof) VD_HIP(hipEventRecord(c->ev[1], s));
-    VD_HIP(vd::launch_clip(a, vd::clip_grid_waves(0, c->num_cu), nullptr, s));
+    VD_HIP(vd::launch_clip(a, vd::clip_grid_workers(0, c->num_cu), nullptr, s));
     if (prof) VD_HIP(hipEventRecord(c->ev[2], s));
     uint32_t hmisc[16];
     VD_HIP(hipMemcpyAsync(hmisc, misc, sizeof(hmisc), hipMemcpyDeviceToHost, s));
@@ -338,14 +338,14 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
         a.next_count = last ? nullptr : misc + 5 + tier;
         a.stage = stage_of(c, tier);
         if (a.ctr) a.ctr = as<unsigned long long>(c->ctr) + tier * vd::kCtrCount;
-        int waves = vd::clip_grid_waves(tier, c->num_cu);
-        if ((int64_t)waves > (int64_t)cnt) waves = (int)cnt;
+        int workers = vd::clip_grid_workers(tier, c->num_cu);
+        if ((int64_t)workers > (int64_t)cnt) workers = (int)cnt;
         void* arena = nullptr;
         if (tier == 3) {
-            VD_TRY(ensure(c->arena, (size_t)waves * vd::arena_bytes_per_wave()));
+            VD_TRY(ensure(c->arena, (size_t)workers * vd::arena_bytes_per_worker()));
             arena = c->arena.p;
         }
-        VD_HIP(vd::launch_clip(a, waves, arena, s));
+        VD_HIP(vd::launch_clip(a, workers, arena, s));
         if (prof && tier == 1) VD_HIP(hipEventRecord(c->ev[6], s));
         VD_HIP(hipMemcpyAsync(hmisc, misc, sizeof(hmisc), hipMemcpyDeviceToHost, s));
         VD_HIP(hipStreamSynchronize(s));

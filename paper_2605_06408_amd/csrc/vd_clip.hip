@@ -28,10 +28,14 @@
 //
 // Capacity tiers: 64 vertices (one slot; vertex state in registers, planes
 // and tables in LDS), 256 (four slots, same layout), 1024 (16 slots; every
-// per-cell array in LDS, one wave per workgroup) and 16384 (256 slots; every
-// per-cell array in a per-wave arena in global memory).  The last two run
-// their slot loops over the slots in use only.  A cell that outgrows a tier
-// is handed to the next.  The paper's own kernel keeps one cell per thread in
+// per-cell array in LDS) and 16384 (256 slots; every per-cell array in an
+// arena in global memory).  In the last two a workgroup of several waves
+// builds one cell: the waves split every loop over vertex slots, combine
+// their partial results through LDS (one barrier per exchange) and repeat
+// the cell-wide control flow in step, so the few very large cells, which
+// set the latency of the whole build, get many waves each; the node queue
+// and the cell's final record belong to the first wave.  A cell that
+// outgrows a tier is handed to the next.  The paper's own kernel keeps one cell per thread in
 // global memory; that layout was made for its GPUs and is not used.
 #include <type_traits>
 
@@ -210,9 +214,13 @@ struct P64 {
 
 // kLds: the per-cell arrays are in LDS (else in global memory).  kCount:
 // count work units and cycles (a separate instantiation, so the timed
-// kernels carry no counting code).
-template <int VPL, bool kLds, bool kCount>
+// kernels carry no counting code).  G: waves building the cell together
+// (one in the register tiers).  Every wave of a group holds the same copy of
+// the cell-wide scalars (site, bounds, plane and queue counts, flags) and
+// changes it the same way, from values every wave has seen.
+template <int VPL, bool kLds, bool kCount, int G = 1>
 struct Cell {
+    static_assert(G == 1 || !Tier<VPL>::kReg, "wave groups need the vertex state in memory");
     using T = Tier<VPL>;
     using W = typename T::W;
     static constexpr int CAP = T::CAP;
@@ -224,6 +232,9 @@ struct Cell {
     WaveMem<VPL>& M;
     const ClipArgs& A;
     const uint32_t ln;
+    const uint32_t wid;  // wave of the group
+    uint32_t* gx;        // group exchange tables in LDS: 2 x G x 8 words
+    int gpar;            // table of the next exchange
     uint32_t serial;
     // site
     float px, py, pz, pw;
@@ -250,7 +261,9 @@ struct Cell {
 
     // the first clip clears the new-vertex tables (the tag counter starts
     // at its wrap-around value)
-    __device__ Cell(WaveMem<VPL>& m, const ClipArgs& a) : M(m), A(a), ln(lane_id()), serial(T::kTagMax - 1) {
+    __device__ Cell(WaveMem<VPL>& m, const ClipArgs& a, uint32_t* gxch)
+        : M(m), A(a), ln(lane_id()), wid(G > 1 ? (uint32_t)(threadIdx.x >> 6) : 0u), gx(gxch), gpar(0),
+          serial(T::kTagMax - 1) {
 #pragma unroll
         for (int c = 0; c < (kCount ? kCtrCount : 1); ++c) ctr[c] = 0;
         if constexpr (!kReg) {
@@ -272,7 +285,84 @@ struct Cell {
     __device__ __forceinline__ void toc(int c, uint64_t t0) {
         if constexpr (kCount) ctr[c] += (uint64_t)clock64() - t0;
     }
-    __device__ __forceinline__ void sync() { wave_sync<kLds>(); }
+    // wsync orders this wave's accesses; sync those of the whole group
+    __device__ __forceinline__ void wsync() { wave_sync<kLds>(); }
+    __device__ __forceinline__ void sync() {
+        if constexpr (G > 1) __syncthreads();
+        else wave_sync<kLds>();
+    }
+    // the first wave of the group (the only one without groups)
+    __device__ __forceinline__ bool lead() const { return G == 1 || wid == 0; }
+    // Group exchange: every wave posts N uniform words; returns the table
+    // (word k of wave w at [w * 8 + k]) once all have posted.  The two tables
+    // alternate, so one barrier per exchange is enough: a wave writes a table
+    // again only after the barrier of the exchange in between, which every
+    // wave reaches after reading it.
+    template <int N>
+    __device__ __forceinline__ const uint32_t* exch(const uint32_t (&v)[N]) {
+        static_assert(N <= 8, "eight words per wave");
+        uint32_t* t = gx + gpar * (G * 8);
+        gpar ^= 1;
+        if (ln == 0) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) t[wid * 8 + k] = v[k];
+        }
+        __syncthreads();
+        return t;
+    }
+    __device__ __forceinline__ bool g_or(bool x) {
+        if constexpr (G == 1) {
+            return x;
+        } else {
+            const uint32_t v[1] = {x ? 1u : 0u};
+            const uint32_t* t = exch(v);
+            bool r = false;
+#pragma unroll
+            for (int w = 0; w < G; ++w) r |= t[w * 8] != 0;
+            return r;
+        }
+    }
+    // the first wave's value, for every wave of the group
+    __device__ __forceinline__ uint32_t bcast(uint32_t x) {
+        if constexpr (G == 1) {
+            return uni(x);
+        } else {
+            const uint32_t v[1] = {x};
+            return exch(v)[0];
+        }
+    }
+    // Sum over the group of a per-wave count: the total, and in *below the
+    // sum over the waves before this one.
+    __device__ __forceinline__ uint32_t g_scan(uint32_t x, uint32_t* below) {
+        if constexpr (G == 1) {
+            *below = 0;
+            return x;
+        } else {
+            const uint32_t v[1] = {x};
+            const uint32_t* t = exch(v);
+            uint32_t tot = 0, bl = 0;
+#pragma unroll
+            for (int w = 0; w < G; ++w) {
+                const uint32_t c = t[w * 8];
+                if (w < (int)wid) bl += c;
+                tot += c;
+            }
+            *below = bl;
+            return tot;
+        }
+    }
+    // This wave's share [lo, hi) of n items dealt in runs of u (the last run
+    // may reach past n, never past the next multiple of u).
+    __device__ __forceinline__ void share(int n, int u, int* lo, int* hi) const {
+        if constexpr (G == 1) {
+            *lo = 0;
+            *hi = n;
+        } else {
+            const int nu = (n + u - 1) / u;
+            *lo = nu * (int)wid / G * u;
+            *hi = nu * ((int)wid + 1) / G * u;
+        }
+    }
     // slots that may hold vertices (all of them in the register tiers)
     __device__ __forceinline__ int nsv() const { return kReg ? VPL : ((vhi + 63) >> 6); }
     __device__ __forceinline__ uint64_t nalive() {
@@ -298,6 +388,7 @@ struct Cell {
 
     // ------------------------------------------------------------ setup
     __device__ bool init(uint32_t k) {
+        if constexpr (G > 1) sync();  // every wave is done with the previous cell
         self = k;
         float4 s = A.pts[k];
         px = s.x; py = s.y; pz = s.z; pw = s.w;
@@ -306,7 +397,7 @@ struct Cell {
         if (pw == -INFINITY) return false;  // coincident with a heavier site
         const float lo[3] = {A.bbox[0] - px, A.bbox[1] - py, A.bbox[2] - pz};
         const float hi[3] = {A.bbox[3] - px, A.bbox[4] - py, A.bbox[5] - pz};
-        if (ln < 6) {
+        if (ln < 6 && lead()) {
             int ax = ln >> 1, side = ln & 1;
             float a[3] = {0.f, 0.f, 0.f};
             a[ax] = side ? 1.f : -1.f;
@@ -321,9 +412,9 @@ struct Cell {
             for (int s2 = 0; s2 < VPL; ++s2) alive[s2] = 0;
         }
         // slots above the first are written by a clip before they are read
-        alive[0] = 0xFFull;
+        if (lead()) alive[0] = 0xFFull;
         vhi = 8;
-        {
+        if (lead()) {
             uint32_t c = ln & 7;
             uint32_t sx = c & 1, sy = (c >> 1) & 1, sz = (c >> 2) & 1;
             uint32_t X = sx, Y = 2 + sy, Z = 4 + sz;
@@ -368,7 +459,9 @@ struct Cell {
         float mn0 = INFINITY, mn1 = INFINITY, mn2 = INFINITY, mx0 = -INFINITY, mx1 = -INFINITY, mx2 = -INFINITY,
               r2 = 0.f;
         const int ns = nsv();
-        for (int s0 = 0; s0 < (kReg ? VPL : ns); s0 += kBatch) {
+        int lo, hi;
+        share(ns, kBatch, &lo, &hi);
+        for (int s0 = (kReg ? 0 : lo); s0 < (kReg ? VPL : hi); s0 += kBatch) {
             VBatch v;
             load_batch(s0, ns, v);
 #pragma unroll
@@ -384,6 +477,23 @@ struct Cell {
         float l0 = wmin(mn0), l1 = wmin(mn1), l2 = wmin(mn2);
         float h0 = wmax(mx0), h1 = wmax(mx1), h2 = wmax(mx2);
         riso2 = wmax(r2);
+        if constexpr (G > 1) {
+            const uint32_t v[7] = {__float_as_uint(l0), __float_as_uint(l1), __float_as_uint(l2), __float_as_uint(h0),
+                                   __float_as_uint(h1), __float_as_uint(h2), __float_as_uint(riso2)};
+            const uint32_t* t = exch(v);
+            l0 = l1 = l2 = INFINITY;
+            h0 = h1 = h2 = -INFINITY;
+            riso2 = 0.f;
+#pragma unroll
+            for (int w = 0; w < G; ++w) {
+                const uint32_t* x = t + w * 8;
+                l0 = fminf(l0, __uint_as_float(x[0])); l1 = fminf(l1, __uint_as_float(x[1]));
+                l2 = fminf(l2, __uint_as_float(x[2]));
+                h0 = fmaxf(h0, __uint_as_float(x[3])); h1 = fmaxf(h1, __uint_as_float(x[4]));
+                h2 = fmaxf(h2, __uint_as_float(x[5]));
+                riso2 = fmaxf(riso2, __uint_as_float(x[6]));
+            }
+        }
         blo0 = l0; blo1 = l1; blo2 = l2;
         bhi0 = h0; bhi1 = h1; bhi2 = h2;
         hx2 = h0 * h0; hy2 = h1 * h1; hz2 = h2 * h2;
@@ -406,7 +516,9 @@ struct Cell {
         if constexpr (kCount) count(kCtrBall, nalive());
         bool hit = false;
         const int ns = nsv();
-        for (int s0 = 0; s0 < (kReg ? VPL : ns); s0 += kBatch) {
+        int lo, hi;
+        share(ns, kBatch, &lo, &hi);
+        for (int s0 = (kReg ? 0 : lo); s0 < (kReg ? VPL : hi); s0 += kBatch) {
             VBatch v;
             load_batch(s0, ns, v);
 #pragma unroll
@@ -423,7 +535,7 @@ struct Cell {
                 }
             }
         }
-        return ballot(hit) != 0;
+        return g_or(ballot(hit) != 0);
     }
 
     // Applies the ball test to the child record held by lane `l`.
@@ -496,7 +608,9 @@ struct Cell {
         bool anyo = false, allo = true;
         Lane<uint8_t> amb;
         if constexpr (!kReg) amb.m = M.amb + ln;
-        for (int s0 = 0; s0 < (kReg ? VPL : ns); s0 += kBatch) {
+        int lo, hi;
+        share(ns, kBatch, &lo, &hi);
+        for (int s0 = (kReg ? 0 : lo); s0 < (kReg ? VPL : hi); s0 += kBatch) {
             VBatch v;
             load_batch(s0, ns, v);
             float e[kBatch];
@@ -526,7 +640,21 @@ struct Cell {
                 allo &= r == v.al[k];
             }
         }
-        if ((mode == 1 || mode == 3) && amb_any) {
+        bool ambf = amb_any != 0;
+        if constexpr (G > 1) {
+            const uint32_t v[3] = {anyo ? 1u : 0u, allo ? 1u : 0u, ambf ? 1u : 0u};
+            const uint32_t* t = exch(v);
+            anyo = false;
+            allo = true;
+            ambf = false;
+#pragma unroll
+            for (int w = 0; w < G; ++w) {
+                anyo |= t[w * 8] != 0;
+                allo &= t[w * 8 + 1] != 0;
+                ambf |= t[w * 8 + 2] != 0;
+            }
+        }
+        if ((mode == 1 || mode == 3) && ambf) {
             flags |= kFlagFP64;
             if constexpr (kCount) {
                 uint64_t na = 0;
@@ -537,8 +665,9 @@ struct Cell {
             P64 h = plane64(hcode, hsite);
             anyo = false;
             allo = true;
+            bool uns = false;
 #pragma unroll
-            for (int s = 0; s < (kReg ? VPL : ns); ++s) {
+            for (int s = (kReg ? 0 : lo); s < (kReg ? VPL : min(hi, ns)); ++s) {
                 bool o = (R[s] >> ln) & 1;
                 bool unsure = false;
                 if (amb[s]) {
@@ -550,8 +679,22 @@ struct Cell {
                 R[s] = r;
                 anyo |= r != 0;
                 allo &= r == alive[s];
-                if (ballot(unsure)) flags |= kFlagUncertain;
+                uns |= ballot(unsure) != 0;
             }
+            if constexpr (G > 1) {
+                const uint32_t v[3] = {anyo ? 1u : 0u, allo ? 1u : 0u, uns ? 1u : 0u};
+                const uint32_t* t = exch(v);
+                anyo = false;
+                allo = true;
+                uns = false;
+#pragma unroll
+                for (int w = 0; w < G; ++w) {
+                    anyo |= t[w * 8] != 0;
+                    allo &= t[w * 8 + 1] != 0;
+                    uns |= t[w * 8 + 2] != 0;
+                }
+            }
+            if (uns) flags |= kFlagUncertain;
         }
         *any_out = anyo;
         *all_out = allo;
@@ -569,9 +712,12 @@ struct Cell {
             gc();
             if (np >= CAP) return kOverflow;
         }
+        int sa, sb;  // this wave's share of the slots in use
+        share(ns, 1, &sa, &sb);
         if constexpr (VPL > 1) {
 #pragma unroll
-            for (int s = 0; s < (kReg ? VPL : ns); ++s) M.outf[s * 64 + ln] = (uint8_t)((R[s] >> ln) & 1);
+            for (int s = (kReg ? 0 : sa); s < (kReg ? VPL : sb); ++s)
+                M.outf[s * 64 + ln] = (uint8_t)((R[s] >> ln) & 1);
             sync();
         }
         auto is_out = [&](uint32_t v) -> bool {
@@ -587,10 +733,11 @@ struct Cell {
             nb1.m = M.nb1 + ln; nb2.m = M.nb2 + ln; rec.m = M.rec + ln; isnew.m = M.isnew + ln;
             fr.m = M.fr;
         }
-        // crossing edges of kept vertices, ranked over the wave
+        // crossing edges of kept vertices, ranked over the wave (over the
+        // group: the counts of lower waves come first)
         uint32_t m = 0;
 #pragma unroll
-        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
+        for (int s = (kReg ? 0 : sa); s < (kReg ? VPL : sb); ++s) {
             bool kept = ((alive[s] & ~R[s]) >> ln) & 1;
             uint32_t c = 0, cnt = 0;
             if (kept) {
@@ -607,16 +754,22 @@ struct Cell {
             pre[s] = m + mbcnt(b0) + 2 * mbcnt(b1);
             m += popc(b0) + 2 * popc(b1);
         }
+        uint32_t pbase;
+        m = g_scan(m, &pbase);
         // free slots (dead or removed), ranked; slots above the used ones are free
         const int nsf = kReg ? VPL : min(VPL, ns + (int)((m + 63) >> 6) + 1);
+        int fa, fb;  // this wave's share of the slots new vertices may take
+        share(nsf, 1, &fa, &fb);
         uint32_t nfree = 0;
 #pragma unroll
-        for (int s = 0; s < (kReg ? VPL : nsf); ++s) {
+        for (int s = (kReg ? 0 : fa); s < (kReg ? VPL : fb); ++s) {
             const uint64_t f = (s < ns) ? (~alive[s] | R[s]) : ~0ull;
             fr[s] = f;
             frank[s] = nfree + mbcnt(f);
             nfree += popc(f);
         }
+        uint32_t fbase;
+        nfree = g_scan(nfree, &fbase);
         if (m == 0) {  // some vertex is cut off but no edge crosses the plane
             *consistent = false;
             return kNone;
@@ -625,22 +778,23 @@ struct Cell {
         const uint32_t h = (uint32_t)np;
         ++serial;
         if (serial >= T::kTagMax) {  // tag space exhausted: clear the tables
-            for (int q = ln; q < CAP; q += 64) { M.ta[q] = 0; M.tb[q] = 0; }
+            for (int q = (int)(wid * 64 + ln); q < CAP; q += 64 * G) { M.ta[q] = 0; M.tb[q] = 0; }
             serial = 1;
         }
         const uint32_t tag = serial << T::kTagShift;
         const uint32_t vmask = (1u << T::kTagShift) - 1u;
 #pragma unroll
-        for (int s = 0; s < (kReg ? VPL : nsf); ++s) {
-            const bool nw = ((fr[s] >> ln) & 1) && frank[s] < m;
+        for (int s = (kReg ? 0 : fa); s < (kReg ? VPL : fb); ++s) {
+            const uint32_t rk = frank[s] + fbase;
+            const bool nw = ((fr[s] >> ln) & 1) && rk < m;
             isnew[s] = nw;
-            if (nw) M.sor[frank[s]] = s * 64 + ln;
+            if (nw) M.sor[rk] = s * 64 + ln;
         }
 #pragma unroll
-        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
+        for (int s = (kReg ? 0 : sa); s < (kReg ? VPL : sb); ++s) {
             const uint32_t c = cross[s];
             if (c) {
-                uint32_t j = pre[s];
+                uint32_t j = pre[s] + pbase;
                 const W t = vt[s];
 #pragma unroll
                 for (int e = 0; e < 3; ++e)
@@ -652,10 +806,10 @@ struct Cell {
         }
         sync();
 #pragma unroll
-        for (int s = 0; s < (kReg ? VPL : nsf); ++s) {
+        for (int s = (kReg ? 0 : fa); s < (kReg ? VPL : fb); ++s) {
             W r = 0;
             if (isnew[s]) {
-                r = M.edge[frank[s]];
+                r = M.edge[frank[s] + fbase];
                 uint32_t me = tag | (uint32_t)(s * 64 + ln);
                 M.ta[T::fld(r, 1)] = me;
                 M.tb[T::fld(r, 2)] = me;
@@ -665,7 +819,7 @@ struct Cell {
         sync();
         bool bad = false;
 #pragma unroll
-        for (int s = 0; s < (kReg ? VPL : nsf); ++s) {
+        for (int s = (kReg ? 0 : fa); s < (kReg ? VPL : fb); ++s) {
             uint32_t n1 = 0, n2 = 0;
             if (isnew[s]) {
                 const W r = rec[s];
@@ -680,7 +834,8 @@ struct Cell {
             nb1[s] = n1;
             nb2[s] = n2;
         }
-        if (!ballot(bad)) {
+        bad = g_or(ballot(bad) != 0);
+        if (!bad) {
             // the new vertices must form one cycle around the new facet:
             // following "next around h" from the first one returns after m steps
             const uint32_t start = uni(M.sor[0]);
@@ -692,8 +847,11 @@ struct Cell {
 #pragma unroll
                     for (int s = 0; s < VPL; ++s)
                         if (s == sl) nxt = rdl(nb1[s], lv);
-                } else {
+                } else if constexpr (G == 1) {
                     if (sl < nsf) nxt = rdl(nb1[sl], lv);
+                } else {
+                    // written by other waves, before the exchange above
+                    if (sl < nsf) nxt = uni(M.nb1[v]);
                 }
                 v = nxt;
                 ++steps;
@@ -706,10 +864,10 @@ struct Cell {
         }
         // commit: kept vertices point at their new neighbours
 #pragma unroll
-        for (int s = 0; s < (kReg ? VPL : ns); ++s) {
+        for (int s = (kReg ? 0 : sa); s < (kReg ? VPL : sb); ++s) {
             const uint32_t c = cross[s];
             if (c) {
-                uint32_t j = pre[s];
+                uint32_t j = pre[s] + pbase;
                 W a = va[s];
 #pragma unroll
                 for (int e = 0; e < 3; ++e)
@@ -719,7 +877,7 @@ struct Cell {
         }
         // new vertices: planes (h, x, y), position by Cramer's rule
 #pragma unroll
-        for (int s = 0; s < (kReg ? VPL : nsf); ++s) {
+        for (int s = (kReg ? 0 : fa); s < (kReg ? VPL : fb); ++s) {
             if (isnew[s]) {
                 const W r = rec[s];
                 uint32_t x = T::fld(r, 1), y = T::fld(r, 2);
@@ -745,7 +903,7 @@ struct Cell {
             }
         }
 #pragma unroll
-        for (int s = 0; s < (kReg ? VPL : nsf); ++s) {
+        for (int s = (kReg ? 0 : fa); s < (kReg ? VPL : fb); ++s) {
             const uint64_t keep = (s < ns) ? (alive[s] & ~R[s]) : 0ull;
             alive[s] = keep | ballot(isnew[s] != 0);
         }
@@ -754,7 +912,7 @@ struct Cell {
             const int top = (int)uni(M.sor[m - 1]) + 1;
             if (top > vhi) vhi = top;
         }
-        if (ln == 0) {
+        if (ln == 0 && lead()) {
             M.pl[h] = make_float4(ax, ay, az, b);
             M.psb[h] = sbh;
             M.pcode[h] = hcode;
@@ -790,10 +948,12 @@ struct Cell {
     // Drop planes no vertex uses (supplementary Sec. A, "Garbage collection").
     __device__ void gc() {
         const int ns = nsv();
-        for (int q = ln; q < np; q += 64) M.key[q] = 0;
+        int sa, sb;
+        share(ns, 1, &sa, &sb);
+        for (int q = (int)(wid * 64 + ln); q < np; q += 64 * G) M.key[q] = 0;
         sync();
 #pragma unroll
-        for (int s = 0; s < (kReg ? VPL : ns); ++s)
+        for (int s = (kReg ? 0 : sa); s < (kReg ? VPL : sb); ++s)
             if ((alive[s] >> ln) & 1) {
                 const W t = vt[s];
                 M.key[T::fld(t, 0)] = 1;
@@ -835,10 +995,10 @@ struct Cell {
                 }
             }
         } else {
-            // in place, 64 planes at a time: a destination never lies above
-            // its source, and every source of a chunk is read before any of
-            // its destinations is written
-            for (int q0 = 0; q0 < np; q0 += 64) {
+            // in place, 64 planes at a time, by the first wave of the group:
+            // a destination never lies above its source, and every source of
+            // a chunk is read before any of its destinations is written
+            for (int q0 = 0; q0 < (lead() ? np : 0); q0 += 64) {
                 const int q = q0 + (int)ln;
                 const bool used = q < np && M.key[q] != 0;
                 const uint64_t u = ballot(used);
@@ -853,7 +1013,7 @@ struct Cell {
                     sb = M.psb[q];
                     pc = M.pcode[q];
                 }
-                sync();
+                wsync();
                 if (used) {
                     M.pl[dst] = pl;
                     M.psite[dst] = ps;
@@ -861,12 +1021,13 @@ struct Cell {
                     M.pcode[dst] = pc;
                     M.key[q] = (int32_t)dst;
                 }
-                sync();
+                wsync();
             }
+            if constexpr (G > 1) cnt = bcast(cnt);
         }
         sync();
 #pragma unroll
-        for (int s = 0; s < (kReg ? VPL : ns); ++s)
+        for (int s = (kReg ? 0 : sa); s < (kReg ? VPL : sb); ++s)
             if ((alive[s] >> ln) & 1) {
                 const W t = vt[s];
                 vt[s] = T::pack3((uint32_t)M.key[T::fld(t, 0)], (uint32_t)M.key[T::fld(t, 1)],
@@ -938,7 +1099,7 @@ struct Cell {
                     qk[s] = k;
                 }
         } else {
-            if ((int)ln == l) {
+            if ((int)ln == l && lead()) {
                 qe[slot] = e;
                 qk[slot] = k;
             }
@@ -947,8 +1108,23 @@ struct Cell {
     }
 
     // Removes and returns the entry with the smallest key (best-first), or
-    // the last pushed one (depth-first).
+    // the last pushed one (depth-first).  The queue is kept by the first wave
+    // of a group, which hands the entry to the others.
     __device__ void pop(uint32_t* e, float* k) {
+        uint32_t ee = 0;
+        float kk = 0.f;
+        if (lead()) pop_lead(&ee, &kk);
+        if constexpr (G > 1) {
+            const uint32_t v[2] = {ee, __float_as_uint(kk)};
+            const uint32_t* t = exch(v);
+            ee = t[0];
+            kk = __uint_as_float(t[1]);
+        }
+        --qn;
+        *e = ee;
+        *k = kk;
+    }
+    __device__ void pop_lead(uint32_t* e, float* k) {
         const int nq = (qn + 63) >> 6;
         int S, L;
         if (A.traversal == 2) {
@@ -1005,7 +1181,6 @@ struct Cell {
                 qk[S] = lk;
             }
         }
-        --qn;
         *e = ee;
         *k = kk;
     }
@@ -1171,8 +1346,16 @@ struct Cell {
 
     // Writes the cell's record.  Returns false if the vertex/facet structure
     // is not a closed simple polytope (the caller then rebuilds the cell).
+    // The planes are compacted by the group, the record written by its first
+    // wave.
     __device__ bool finalize(uint32_t slot, uint32_t orig) {
         gc();
+        bool ok = true;
+        if (lead()) ok = finalize_lead(slot, orig);
+        if constexpr (G > 1) ok = bcast(ok ? 1u : 0u) != 0;
+        return ok;
+    }
+    __device__ bool finalize_lead(uint32_t slot, uint32_t orig) {
         const int F = np;
         const int ns = nsv();
         // facet order: ascending output code (box faces -6..-1, then original site ids)
@@ -1180,7 +1363,7 @@ struct Cell {
             int32_t c = M.pcode[q];
             M.key[q] = c >= 0 ? (int32_t)A.order[c] : c;
         }
-        sync();
+        wsync();
         for (int q = ln; q < F; q += 64) {
             int32_t mine = M.key[q];
             uint32_t r = 0;
@@ -1202,7 +1385,7 @@ struct Cell {
             if ((al >> ln) & 1) M.sor[s * 64 + ln] = nv + mbcnt(al);
             nv += popc(al);
         }
-        sync();
+        wsync();
         if (s0 < 0) return false;
         // reference point of the tetrahedral fan: vertex 0, in FP64
         double ref[3] = {0.0, 0.0, 0.0};
@@ -1266,7 +1449,7 @@ struct Cell {
                 atomicMin(&M.anchor[t2], v);
             }
         }
-        sync();
+        wsync();
         // facet rings in output (rank) order, counter-clockwise seen from outside;
         // sizes and anchors (lowest vertex) are indexed by facet rank
         uint16_t* fs = st.fsize + (int64_t)slot * st.cap;
@@ -1346,7 +1529,7 @@ struct Cell {
     }
 
     __device__ void write_empty(uint32_t orig, uint32_t extra) {
-        if (ln == 0) {
+        if (ln == 0 && lead()) {
             A.cnt_v[orig] = 0;
             A.cnt_f[orig] = 0;
             A.cnt_n[orig] = 0;
@@ -1360,10 +1543,11 @@ struct Cell {
     }
 };
 
-// The per-wave work loop shared by every tier.
-template <int VPL, bool kLds, bool kCount>
-__device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A) {
-    Cell<VPL, kLds, kCount> C(M, A);
+// The work loop shared by every tier (per wave, or per wave group with gx
+// its exchange tables).
+template <int VPL, bool kLds, bool kCount, int G = 1>
+__device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
+    Cell<VPL, kLds, kCount, G> C(M, A, gx);
     const uint32_t count = A.list ? *A.list_count : (uint32_t)A.n;
     unsigned long long st_empty = 0, st_large = 0, st_unc = 0, st_fail = 0, st_fp64 = 0;
     // Cells are split into kWorkRanges contiguous (Morton-ordered) ranges, one
@@ -1380,8 +1564,8 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A) {
                 const uint32_t lo = (uint32_t)((uint64_t)count * r / kWorkRanges);
                 const uint32_t hi = (uint32_t)((uint64_t)count * (r + 1) / kWorkRanges);
                 uint32_t c0 = 0;
-                if (C.ln == 0) c0 = atomicAdd(&A.work_counter[r], (uint32_t)kWorkChunk);
-                c0 = uni(c0);
+                if (C.ln == 0 && C.lead()) c0 = atomicAdd(&A.work_counter[r], (uint32_t)kWorkChunk);
+                c0 = C.bcast(c0);
                 if (c0 < hi - lo) {
                     cur = lo + c0;
                     end = min(hi, cur + (uint32_t)kWorkChunk);
@@ -1419,7 +1603,7 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A) {
             }
             if (r == kOverflow) {
                 if (A.next_list) {
-                    if (C.ln == 0) A.next_list[atomicAdd(A.next_count, 1u)] = k;
+                    if (C.ln == 0 && C.lead()) A.next_list[atomicAdd(A.next_count, 1u)] = k;
                     escalated = true;
                 } else {
                     C.write_empty(orig, kFlagFailed);
@@ -1462,7 +1646,7 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A) {
         st_unc += (C.flags & kFlagUncertain) ? 1 : 0;
         st_fp64 += (C.flags & kFlagFP64) ? 1 : 0;
     }
-    if (C.ln == 0) {
+    if (C.ln == 0 && C.lead()) {
         if constexpr (kCount)
             for (int c = 0; c < kCtrCount; ++c)
                 if (C.ctr[c]) atomicAdd(&A.ctr[c], (unsigned long long)C.ctr[c]);
@@ -1474,34 +1658,50 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A) {
     }
 }
 
-// LDS tiers: per-cell arrays in LDS, WAVES independent waves per block.
-// Register budgets: the 64-vertex pass is held to 128 registers for 4 waves
-// per SIMD, the 256-vertex pass to 256 for 2 (a few spills cost less than
-// the lost occupancy: both passes issue VALU work back to back).
+// Register tiers: per-cell arrays in LDS, WAVES independent waves per
+// block.  Register budgets: the 64-vertex pass is held to 128 registers for
+// 4 waves per SIMD, the 256-vertex pass to 256 for 2 (a few spills cost less
+// than the lost occupancy: both passes issue VALU work back to back).
 template <int VPL, int WAVES, bool kCount>
-__global__ __launch_bounds__(64 * WAVES, VPL == 1 ? 4 : (VPL == 4 ? 2 : 1)) void k_clip(ClipArgs A) {
+__global__ __launch_bounds__(64 * WAVES, VPL == 1 ? 4 : 2) void k_clip(ClipArgs A) {
     __shared__ WaveMem<VPL> mem[WAVES];
-    run_cells<VPL, true, kCount>(mem[threadIdx.x >> 6], A);
+    run_cells<VPL, true, kCount>(mem[threadIdx.x >> 6], A, nullptr);
 }
 
-// Arena tier: one wave per block, its per-cell arrays in arena[blockIdx.x].
+// Waves per cell in the 1024-vertex (LDS) and 16384-vertex (arena) tiers.
+constexpr int kGroupLds = 4;
+constexpr int kGroupArena = 8;
+
+// 1024-vertex tier: the kGroupLds waves of a block build one cell, its
+// arrays in LDS (one block per CU).
+template <bool kCount>
+__global__ __launch_bounds__(64 * kGroupLds, 1) void k_clip_lds(ClipArgs A) {
+    __shared__ WaveMem<16> mem;
+    __shared__ uint32_t gx[2 * kGroupLds * 8];
+    run_cells<16, true, kCount, kGroupLds>(mem, A, gx);
+}
+
+// 16384-vertex tier: the kGroupArena waves of a block build one cell, its
+// arrays in arena[blockIdx.x].
 constexpr int kArenaVPL = kTierCap[3] / 64;
 template <bool kCount>
-__global__ __launch_bounds__(64) void k_clip_arena(ClipArgs A, WaveMem<kArenaVPL>* arena) {
-    run_cells<kArenaVPL, false, kCount>(arena[blockIdx.x], A);
+__global__ __launch_bounds__(64 * kGroupArena) void k_clip_arena(ClipArgs A, WaveMem<kArenaVPL>* arena) {
+    __shared__ uint32_t gx[2 * kGroupArena * 8];
+    run_cells<kArenaVPL, false, kCount, kGroupArena>(arena[blockIdx.x], A, gx);
 }
 
 static_assert(kTierCap[0] == 64 && kTierCap[1] == 256 && kTierCap[2] == 1024,
               "the LDS tiers are instantiated for 64, 256 and 1024 vertices");
-static_assert(sizeof(WaveMem<16>) <= 160 * 1024, "the 1024-vertex tier must fit the LDS of one CU");
+static_assert(sizeof(WaveMem<16>) + 2 * kGroupLds * 8 * sizeof(uint32_t) <= 160 * 1024,
+              "the 1024-vertex tier must fit the LDS of one CU");
 static_assert(Tier<kArenaVPL>::CAP <= (1 << Tier<kArenaVPL>::kB) && Tier<kArenaVPL>::CAP <= (1 << 16),
               "arena-tier indices must fit their packings and the 16-bit staged facet lists");
 
 }  // namespace
 
-size_t arena_bytes_per_wave() { return sizeof(WaveMem<kArenaVPL>); }
+size_t arena_bytes_per_worker() { return sizeof(WaveMem<kArenaVPL>); }
 
-int clip_grid_waves(int tier, int num_cu) {
+int clip_grid_workers(int tier, int num_cu) {
     int per_cu = 0;
     hipError_t e = hipSuccess;
     if (tier == 0) {
@@ -1511,37 +1711,40 @@ int clip_grid_waves(int tier, int num_cu) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip<4, 2, false>, 128, 0);
         per_cu *= 2;
     } else if (tier == 2) {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip<16, 1, false>, 64, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip_lds<false>, 64 * kGroupLds, 0);
+        if (e == hipSuccess && per_cu > 0) return per_cu * num_cu;
+        return num_cu;
     } else {
-        per_cu = 2;  // arena waves: bounded by arena memory, not by occupancy
+        return num_cu;  // arena groups: one per CU, bounded by arena memory
     }
     if (e != hipSuccess || per_cu < 1) per_cu = 4;
     return per_cu * num_cu;
 }
 
 template <bool kCount>
-void launch_tier(const ClipArgs& a, int grid_waves, void* arena, hipStream_t s) {
+void launch_tier(const ClipArgs& a, int workers, void* arena, hipStream_t s) {
     switch (a.tier) {
         case 0:
-            hipLaunchKernelGGL((k_clip<1, 4, kCount>), dim3((grid_waves + 3) / 4), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_clip<1, 4, kCount>), dim3((workers + 3) / 4), dim3(256), 0, s, a);
             break;
         case 1:
-            hipLaunchKernelGGL((k_clip<4, 2, kCount>), dim3((grid_waves + 1) / 2), dim3(128), 0, s, a);
+            hipLaunchKernelGGL((k_clip<4, 2, kCount>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
             break;
         case 2:
-            hipLaunchKernelGGL((k_clip<16, 1, kCount>), dim3(grid_waves), dim3(64), 0, s, a);
+            hipLaunchKernelGGL((k_clip_lds<kCount>), dim3(workers), dim3(64 * kGroupLds), 0, s, a);
             break;
         default:
-            hipLaunchKernelGGL((k_clip_arena<kCount>), dim3(grid_waves), dim3(64), 0, s, a,
+            hipLaunchKernelGGL((k_clip_arena<kCount>), dim3(workers), dim3(64 * kGroupArena), 0, s, a,
                                static_cast<WaveMem<kArenaVPL>*>(arena));
             break;
     }
 }
 
-hipError_t launch_clip(const ClipArgs& a, int grid_waves, void* arena, hipStream_t s) {
+hipError_t launch_clip(const ClipArgs& a, int workers, void* arena, hipStream_t s) {
     if (a.tier >= 3 && !arena) return hipErrorInvalidValue;
-    if (a.ctr) launch_tier<true>(a, grid_waves, arena, s);
-    else launch_tier<false>(a, grid_waves, arena, s);
+    if (workers < 1) return hipErrorInvalidValue;
+    if (a.ctr) launch_tier<true>(a, workers, arena, s);
+    else launch_tier<false>(a, workers, arena, s);
     return hipGetLastError();
 }
 

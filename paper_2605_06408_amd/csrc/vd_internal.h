@@ -186,11 +186,13 @@ hipError_t scan_counts(const uint32_t* in, int64_t n, int64_t* out, int64_t* tmp
 // Exclusive scan of uint32 -> uint32 (for radix histograms).
 hipError_t scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* tmp, hipStream_t s);
 
-// Waves to launch for a clipping pass, and the per-wave arena the last pass
-// (tier 3) needs: launch_clip(tier 3) takes grid_waves * arena_bytes_per_wave().
-int clip_grid_waves(int tier, int num_cu);
-size_t arena_bytes_per_wave();
-hipError_t launch_clip(const ClipArgs& a, int grid_waves, void* arena, hipStream_t s);
+// Cell workers to launch for a clipping pass (a wave in the two register
+// tiers, a workgroup of waves sharing one cell in the two larger ones), and
+// the per-worker arena the last pass (tier 3) needs: launch_clip(tier 3)
+// takes workers * arena_bytes_per_worker().
+int clip_grid_workers(int tier, int num_cu);
+size_t arena_bytes_per_worker();
+hipError_t launch_clip(const ClipArgs& a, int workers, void* arena, hipStream_t s);
 hipError_t launch_set_i64(int64_t* dst, int64_t value, hipStream_t s);
 hipError_t launch_write(const WriteArgs& a, hipStream_t s);
 hipError_t launch_backward(const BwdArgs& a, hipStream_t s);
