@@ -58,7 +58,8 @@ class Options(ctypes.Structure):
 
 class Sizes(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("n", "n_nbr", "n_facet", "n_vert", "n_fv", "n_empty", "n_large",
-                                               "n_uncertain", "n_failed", "n_fp64", "n_huge")]
+                                               "n_uncertain", "n_failed", "n_fp64", "n_huge",
+                                               "n_resumed")]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -38,6 +38,7 @@ struct vd_context {
     DevBuf lists[vd::kTiers];  // lists[t]: cells handed on to tier t (t >= 1)
     DevBuf st_vert[vd::kTiers], st_tri64[vd::kTiers], st_code[vd::kTiers], st_fsize[vd::kTiers], st_fv[vd::kTiers];
     DevBuf arena;  // per-worker cell arrays of the last (16384-vertex) pass
+    DevBuf handoff;  // cells the 1024-vertex pass hands to the last one
     DevBuf bwd_facet, bwd_self, bwd_orphan;  // backward scratch
     // last build
     bool valid = false;
@@ -156,7 +157,7 @@ VD_API void vd_destroy(vd_context* c) {
                      &c->child, &c->pint, &c->pleaf, &c->range, &c->counters, &c->nodes, &c->hist, &c->stmp,
                      &c->bbox, &c->bpart, &c->misc, &c->loc, &c->cnt_v, &c->cnt_f, &c->cnt_n, &c->vol, &c->cen,
                      &c->flags, &c->offv, &c->offf, &c->offn, &c->scan_tmp, &c->stats,
-                     &c->ctr, &c->arena, &c->bwd_facet, &c->bwd_self, &c->bwd_orphan};
+                     &c->ctr, &c->arena, &c->handoff, &c->bwd_facet, &c->bwd_self, &c->bwd_orphan};
     for (DevBuf* b : all) release(*b);
     if (c->ev_ready)
         for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -338,6 +339,17 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
         a.next_count = last ? nullptr : misc + 5 + tier;
         a.stage = stage_of(c, tier);
         if (a.ctr) a.ctr = as<unsigned long long>(c->ctr) + tier * vd::kCtrCount;
+        // hand-over records: written by tier 2 for the first kHandoffMax
+        // cells it escalates, read by tier 3
+        if (tier == 2) {
+            const uint32_t cap = cnt < (uint32_t)vd::kHandoffMax ? cnt : (uint32_t)vd::kHandoffMax;
+            VD_TRY(ensure(c->handoff, (size_t)cap * sizeof(vd::Handoff)));
+            a.handoff = as<vd::Handoff>(c->handoff);
+            a.handoff_cap = cap;
+        } else if (tier != 3) {
+            a.handoff = nullptr;
+            a.handoff_cap = 0;
+        }
         int workers = vd::clip_grid_workers(tier, c->num_cu);
         if ((int64_t)workers > (int64_t)cnt) workers = (int)cnt;
         void* arena = nullptr;
@@ -381,6 +393,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     z.n_failed = (int64_t)st[vd::kStatFailed];
     z.n_fp64 = (int64_t)st[vd::kStatFP64];
     z.n_huge = c->tier_slots[3];
+    z.n_resumed = (int64_t)st[vd::kStatResumed];
     c->sizes = z;
     c->n = n;
     c->order = order;

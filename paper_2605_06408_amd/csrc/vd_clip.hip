@@ -255,6 +255,11 @@ struct Cell {
     Lane<uint32_t> qe;
     Lane<float> qk;
     int qn;
+    // where the last capacity overflow struck: in leaf ov_leaf, with the
+    // candidates ov_mask still to try (ov_ok), else somewhere not resumable
+    bool ov_ok;
+    uint32_t ov_leaf;
+    uint64_t ov_mask;
     // work counters (uniform), accumulated over all cells of this wave
     uint64_t ctr[kCount ? kCtrCount : 1];
     static constexpr bool counting = kCount;
@@ -436,9 +441,10 @@ struct Cell {
 
     // Slots are visited kBatch at a time: in the LDS and arena tiers every
     // load of a batch is issued before any is used (one wait per batch, not
-    // per slot).  Slots at or above ns read as dead (the loads stay in
-    // bounds: VPL is a multiple of kBatch).
-    static constexpr int kBatch = kReg ? VPL : 4;
+    // per slot); wave groups deal the slots out two at a time, so that a
+    // cell of few slots still keeps every wave busy.  Slots at or above ns
+    // read as dead (the loads stay in bounds: VPL is a multiple of kBatch).
+    static constexpr int kBatch = kReg ? VPL : (G > 1 ? 2 : 4);
     struct VBatch {
         float a[kBatch], b[kBatch], c[kBatch];
         uint64_t al[kBatch];
@@ -1185,8 +1191,9 @@ struct Cell {
         *k = kk;
     }
 
-    // Clips by the candidate sites of one leaf; nearest plane first.
-    __device__ int leaf(uint32_t ref) {
+    // Clips by the candidate sites of one leaf (those of lanes in `allow`);
+    // nearest plane first.
+    __device__ int leaf(uint32_t ref, uint64_t allow) {
         const uint32_t first = leaf_first(ref), nsite = leaf_count(ref);
         count(kCtrLeaf, 1);
         count(kCtrSite, nsite);
@@ -1219,6 +1226,7 @@ struct Cell {
             return !(t > 0.f && t * t > a2 * r2);
         };
         uint64_t mask = ballot(keep(cand));
+        if constexpr (CAP > kHandoffCap) mask &= allow;
         while (mask) {
             int L;
             if (A.traversal == 2) {
@@ -1236,6 +1244,13 @@ struct Cell {
             const uint64_t t0 = tic();
             int r = clip(hx, hy, hz, hb, sb, (int32_t)(first + (uint32_t)L), hs);
             toc(kCtrCycClip, t0);
+            if constexpr (CAP == kHandoffCap) {
+                if (r == kOverflow) {  // the cell is as before this candidate
+                    ov_ok = true;
+                    ov_leaf = ref;
+                    ov_mask = mask | (1ull << L);
+                }
+            }
             if (r == kEmptied || r == kOverflow || r == kRestart) return r;
             if (r == kChanged) {
                 update_bounds();
@@ -1253,9 +1268,19 @@ struct Cell {
     }
 
     // Alg. 1.  Returns kNone when done, kEmptied, kOverflow or kRestart.
-    __device__ int traverse() {
+    // A cell taken over from the previous pass (resume) first finishes the
+    // leaf it stopped in, then goes on with the queue it brought.
+    __device__ int traverse(bool resume = false, uint32_t rleaf = 0, uint64_t rmask = 0) {
         uint32_t cur = A.root;
         bool have = true;
+        uint64_t allow = ~0ull;  // candidates of the first leaf
+        if constexpr (CAP > kHandoffCap) {
+            if (resume) {
+                cur = rleaf;
+                allow = rmask;
+            }
+        }
+        if constexpr (CAP == kHandoffCap) ov_ok = false;
         // every node is visited at most once in a valid tree; the bound only
         // guarantees termination if the tree were ever malformed
         int64_t budget = 4 * A.n + 1024;
@@ -1295,7 +1320,8 @@ struct Cell {
             }
             if (have) {
                 const uint64_t t0 = tic();
-                int r = leaf(cur);
+                int r = leaf(cur, allow);
+                if constexpr (CAP > kHandoffCap) allow = ~0ull;
                 toc(kCtrCycLeaf, t0);
                 if (r != kNone) return r;
             }
@@ -1328,6 +1354,87 @@ struct Cell {
                 }
             }
             if (!have) return kNone;
+        }
+    }
+
+    // ------------------------------------------------------------ hand-over
+    // Writes the state of a cell that overflowed (1024-vertex pass) for the
+    // next pass; only the header when the overflow is not resumable.
+    __device__ void save(Handoff& H) {
+        if constexpr (!kReg && CAP == kHandoffCap) {
+            sync();
+            const int tid = (int)(wid * 64 + ln), step = 64 * G;
+            if (ov_ok) {
+                for (int q = tid; q < np; q += step) {
+                    H.pl[q] = M.pl[q];
+                    H.psite[q] = M.psite[q];
+                    H.psb[q] = M.psb[q];
+                    H.pcode[q] = M.pcode[q];
+                }
+                for (int q = tid; q < vhi; q += step) {
+                    H.y0[q] = M.y0[q];
+                    H.y1[q] = M.y1[q];
+                    H.y2[q] = M.y2[q];
+                    H.ev[q] = M.ev[q];
+                    H.vt[q] = M.vt[q];
+                    H.va[q] = M.va[q];
+                }
+                for (int q = tid; q < qn; q += step) {
+                    H.qe[q] = M.qe[q];
+                    H.qk[q] = M.qk[q];
+                }
+                if (tid < nsv()) H.alive[tid] = M.alive[tid];
+            }
+            if (tid == 0) {
+                H.np = (uint32_t)np;
+                H.vhi = (uint32_t)vhi;
+                H.qn = (uint32_t)qn;
+                H.flags = flags;
+                H.robust = (uint32_t)robust;
+                H.leaf = ov_leaf;
+                H.mask = ov_mask;
+                H.valid = ov_ok ? 1u : 0u;
+            }
+        }
+    }
+
+    // Takes over a cell saved by the 1024-vertex pass (instead of init):
+    // the traversal then goes on with resume = true, H.leaf, H.mask.
+    __device__ void resume(uint32_t k, const Handoff& H) {
+        if constexpr (!kReg && CAP > kHandoffCap) {
+            sync();  // every wave is done with the previous cell
+            self = k;
+            float4 s = A.pts[k];
+            px = s.x; py = s.y; pz = s.z; pw = s.w;
+            flags = H.flags;
+            robust = (int)H.robust;
+            np = (int)H.np;
+            vhi = (int)H.vhi;
+            qn = (int)H.qn;
+            const int tid = (int)(wid * 64 + ln), step = 64 * G;
+            for (int q = tid; q < np; q += step) {
+                M.pl[q] = H.pl[q];
+                M.psite[q] = H.psite[q];
+                M.psb[q] = H.psb[q];
+                M.pcode[q] = H.pcode[q];
+            }
+            // vertex and plane indices: ten bits each there, wider here
+            auto wide = [](uint32_t x) { return T::pack3(x & 1023u, (x >> 10) & 1023u, (x >> 20) & 1023u); };
+            for (int q = tid; q < vhi; q += step) {
+                M.y0[q] = H.y0[q];
+                M.y1[q] = H.y1[q];
+                M.y2[q] = H.y2[q];
+                M.ev[q] = H.ev[q];
+                M.vt[q] = wide(H.vt[q]);
+                M.va[q] = wide(H.va[q]);
+            }
+            for (int q = tid; q < qn; q += step) {
+                M.qe[q] = H.qe[q];
+                M.qk[q] = H.qk[q];
+            }
+            if (tid < nsv()) M.alive[tid] = H.alive[tid];
+            sync();
+            update_bounds();
         }
     }
 
@@ -1549,7 +1656,7 @@ template <int VPL, bool kLds, bool kCount, int G = 1>
 __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
     Cell<VPL, kLds, kCount, G> C(M, A, gx);
     const uint32_t count = A.list ? *A.list_count : (uint32_t)A.n;
-    unsigned long long st_empty = 0, st_large = 0, st_unc = 0, st_fail = 0, st_fp64 = 0;
+    unsigned long long st_empty = 0, st_large = 0, st_unc = 0, st_fail = 0, st_fp64 = 0, st_res = 0;
     // Cells are split into kWorkRanges contiguous (Morton-ordered) ranges, one
     // per XCD: the waves of workgroup b take chunks of their own range b % 8
     // first, so neighbouring cells (which walk the same nodes and sites) share
@@ -1581,6 +1688,10 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
         const uint32_t k = A.list ? A.list[c] : c;
         const uint32_t slot = A.list ? c : k;
         const uint32_t orig = A.order[k];
+        // a cell the previous pass handed over goes on from where it stopped
+        const Handoff* hin = nullptr;
+        if constexpr (Tier<VPL>::CAP > kHandoffCap)
+            if (A.handoff && c < A.handoff_cap && A.handoff[c].valid) hin = &A.handoff[c];
         // a cell is built with plain FP32 signs first (mixed mode: with FP64
         // re-evaluation of doubtful ones); if that meets an inconsistent
         // configuration it is rebuilt with the FP64 re-evaluation, then with
@@ -1588,14 +1699,18 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
         C.robust = A.precision == 2 ? 1 : 0;
         bool done = false, escalated = false, loser = false;
         for (int attempt = 0; attempt < 3 && !done; ++attempt) {
-            if (!C.init(k)) {
+            const bool res = attempt == 0 && hin != nullptr;
+            if (res) {
+                C.resume(k, *hin);
+                ++st_res;
+            } else if (!C.init(k)) {
                 loser = true;
                 break;
             }
             if (attempt > 0) C.flags |= kFlagFP64;
             if (A.tier > 0) C.flags |= kFlagLarge;
             const uint64_t t0 = C.tic();
-            int r = C.traverse();
+            int r = C.traverse(res, res ? hin->leaf : 0u, res ? hin->mask : 0ull);
             C.toc(kCtrCycTraverse, t0);
             if (r == kRestart) {
                 C.robust = C.robust + 1;
@@ -1603,7 +1718,15 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
             }
             if (r == kOverflow) {
                 if (A.next_list) {
-                    if (C.ln == 0 && C.lead()) A.next_list[atomicAdd(A.next_count, 1u)] = k;
+                    uint32_t pos = 0;
+                    if (C.ln == 0 && C.lead()) {
+                        pos = atomicAdd(A.next_count, 1u);
+                        A.next_list[pos] = k;
+                    }
+                    if constexpr (Tier<VPL>::CAP == kHandoffCap) {
+                        pos = C.bcast(pos);
+                        if (A.handoff && pos < A.handoff_cap) C.save(A.handoff[pos]);
+                    }
                     escalated = true;
                 } else {
                     C.write_empty(orig, kFlagFailed);
@@ -1655,6 +1778,7 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
         if (st_unc) atomicAdd(&A.stats[kStatUncertain], st_unc);
         if (st_fail) atomicAdd(&A.stats[kStatFailed], st_fail);
         if (st_fp64) atomicAdd(&A.stats[kStatFP64], st_fp64);
+        if (st_res) atomicAdd(&A.stats[kStatResumed], st_res);
     }
 }
 

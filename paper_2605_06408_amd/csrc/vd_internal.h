@@ -74,10 +74,32 @@ __host__ __device__ inline uint32_t make_loc(uint32_t tier, uint32_t slot) { ret
 constexpr uint32_t kFlagEmpty = 1u, kFlagFP64 = 2u, kFlagLarge = 4u, kFlagUncertain = 8u, kFlagFailed = 16u;
 
 // Build statistics accumulated by the clip kernels (device, uint64 each).
-enum StatIndex { kStatEmpty = 0, kStatLarge, kStatUncertain, kStatFailed, kStatFP64, kStatCount };
+enum StatIndex { kStatEmpty = 0, kStatLarge, kStatUncertain, kStatFailed, kStatFP64, kStatResumed, kStatCount };
 // Work counters (mirror VD_CTR_* in vd.h).
 enum CtrIndex { kCtrClassify = 0, kCtrNewVertex, kCtrNode, kCtrSite, kCtrFinal, kCtrClip, kCtrEffective, kCtrLeaf,
                 kCtrBall, kCtrFP64, kCtrCycTraverse, kCtrCycLeaf, kCtrCycClip, kCtrCycFinal, kCtrCount };
+
+// State of a cell that outgrew the 1024-vertex pass while clipping by the
+// sites of a leaf, handed to the 16384-vertex pass so that the cell goes on
+// from there instead of starting over: vertices (same numbering, indices
+// packed ten bits each as in the 1024-vertex pass), planes, node queue, and
+// the leaf with its candidates not yet tried.
+constexpr int kHandoffCap = 1024;   // vertices, planes and queue entries (kTierCap[2])
+constexpr int kHandoffMax = 256;    // cells handed over per build (later ones start over)
+struct Handoff {
+    float4 pl[kHandoffCap];       // planes: a.xyz, b
+    float4 psite[kHandoffCap];    // the plane's site
+    unsigned long long alive[kHandoffCap / 64];
+    unsigned long long mask;      // candidates of the leaf still to try (lanes)
+    float y0[kHandoffCap], y1[kHandoffCap], y2[kHandoffCap], ev[kHandoffCap];
+    uint32_t vt[kHandoffCap], va[kHandoffCap];
+    float psb[kHandoffCap];
+    int32_t pcode[kHandoffCap];
+    uint32_t qe[kHandoffCap];
+    float qk[kHandoffCap];
+    uint32_t valid;               // 1: the state above can be resumed
+    uint32_t np, vhi, qn, flags, robust, leaf;
+};
 
 struct ClipArgs {
     const float4* pts;        // sites in Morton order: x, y, z, w (w = -inf: coincident loser)
@@ -98,6 +120,10 @@ struct ClipArgs {
     const uint32_t* list_count;   // device count (list != null), else count = n
     uint32_t* next_list;      // escalation list for the next tier (null: last tier)
     uint32_t* next_count;
+    // tier 2 writes, tier 3 reads the hand-over of escalated cell c (list
+    // position) for c < handoff_cap; null elsewhere
+    Handoff* handoff;
+    uint32_t handoff_cap;
     Stage stage;
     uint32_t* loc;            // [n] by Morton position
     uint32_t* cnt_v;          // [n] by original index

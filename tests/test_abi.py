@@ -60,5 +60,10 @@ def test_null_arguments_are_rejected_on_the_host(lib):
 def test_struct_layouts_match_header():
     import paper_2605_06408_amd as vd
     assert ctypes.sizeof(vd.Options) == 32
-    assert ctypes.sizeof(vd.Sizes) == 88
+    # one int64 per field the header declares in vd_sizes, in the same order
+    hdr = open(HEADER).read()
+    body = re.search(r"typedef struct vd_sizes \{(.*?)\} vd_sizes;", hdr, re.S).group(1)
+    names = re.findall(r"int64_t\s+(\w+);", body)
+    assert [f[0] for f in vd.Sizes._fields_] == names
+    assert ctypes.sizeof(vd.Sizes) == 8 * len(names)
     assert ctypes.sizeof(vd.Outputs) == 12 * 8

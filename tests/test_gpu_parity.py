@@ -223,7 +223,8 @@ def _walled_site(n, m, seed):
 @pytest.mark.parametrize("kind,precision", [("heavy", 1), ("heavy", 2), ("walled", 1)])
 def test_very_large_cells(oracle_mod, kind, precision):
     """Cells of hundreds to thousands of vertices (built by several waves
-    together in the two largest passes).  With so many planes some vertex is
+    together in the two largest passes; the largest handed from one to the
+    other mid-way).  With so many planes some vertex is
     always within FP32 rounding of a foreign plane, so the oracle cannot
     certify these cells; they are held to the volume and centroid bar and to
     nearly the same neighbours, the rest of the diagram to the usual parity
@@ -233,6 +234,8 @@ def test_very_large_cells(oracle_mod, kind, precision):
     d = gpu_build(xyz, w, box, precision=precision)
     assert d.sizes["n_failed"] == 0
     assert d.sizes["n_huge"] >= 1
+    # cells that outgrew 1024 vertices mid-leaf go on from that state
+    assert 1 <= d.sizes["n_resumed"] <= d.sizes["n_huge"]
     g_all = to_numpy(d)
     assert g_all["vol"].astype(np.float64).sum() == pytest.approx(1.0, rel=1e-5)
     rng = np.random.default_rng(5)
