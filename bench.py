@@ -261,7 +261,7 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.config, "n": n, "seed": args.seed, "box": bbox,
                    "weights": w is not None, "precision": "fp32" if args.precision == 1 else "mixed fp32/fp64",
-                   "leaf_size": args.leaf_size or 16, "culling": args.culling, "traversal": args.traversal},
+                   "leaf_size": args.leaf_size or 32, "culling": args.culling, "traversal": args.traversal},
         "roofline": roofline,
         "phases_ms": phases,
         "counters": ctr,

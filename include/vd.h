@@ -54,7 +54,7 @@ typedef enum {
 /* Options; pass NULL for the defaults.  Zero in any field means its default. */
 typedef struct vd_options {
     int32_t precision;  /* 1 = FP32 predicates (default), 2 = mixed FP32 / FP64 */
-    int32_t leaf_size;  /* sites per BVH leaf, 1..64 (default 16) */
+    int32_t leaf_size;  /* sites per BVH leaf, 1..64 (default 32) */
     int32_t culling;    /* 1 = directional (Sec. 4.2.1-4.2.2), 2 = isotropic radius,
                            3 = directional plus vertex power-ball node test and
                                exact plane-versus-cell-box site test (default) */

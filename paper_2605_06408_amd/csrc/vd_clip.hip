@@ -94,6 +94,12 @@ __device__ __forceinline__ float wmax(float v) {
         return __float_as_int(fmaxf(__int_as_float(a), __int_as_float(b)));
     }));
 }
+__device__ __forceinline__ uint64_t wor64(uint64_t v) {
+    auto op = [](int a, int b) { return a | b; };
+    const uint32_t lo = (uint32_t)wave_reduce_i((int)(uint32_t)v, 0, true, op);
+    const uint32_t hi = (uint32_t)wave_reduce_i((int)(uint32_t)(v >> 32), 0, true, op);
+    return (uint64_t)lo | ((uint64_t)hi << 32);
+}
 __device__ __forceinline__ uint32_t wsum_u(uint32_t v) {
     return (uint32_t)wave_reduce_i((int)v, 0, false, [](int a, int b) { return (int)((uint32_t)a + (uint32_t)b); });
 }
@@ -1191,6 +1197,52 @@ struct Cell {
         *k = kk;
     }
 
+    // The candidates of `mask` (plane of lane L: a, b, size sb) that have
+    // some vertex of the cell outside, or, when doubtful signs are
+    // re-evaluated, within rounding of it.  A plane that misses the cell
+    // misses every cell it is later clipped to, so the others need no clip:
+    // for a wave group this is one pass and one exchange for the whole leaf
+    // instead of one clip each.  The test is the FP32 side test of classify.
+    __device__ uint64_t cutting(uint64_t mask, float ax, float ay, float az, float b, float sb) {
+        const int ns = nsv();
+        int lo, hi;
+        share(ns, kBatch, &lo, &hi);
+        const bool tol = robust != 0;
+        if constexpr (kCount) count(kCtrClassify, nalive() * (uint64_t)popc(mask));
+        uint64_t cb = 0;  // candidates this lane's vertices put outside
+        for (int s0 = (kReg ? 0 : lo); s0 < (kReg ? VPL : hi); s0 += kBatch) {
+            VBatch v;
+            load_batch(s0, ns, v);
+            float e[kBatch];
+            if (tol) {
+#pragma unroll
+                for (int k = 0; k < kBatch; ++k) e[k] = ev[s0 + k];
+            }
+            for (uint64_t m = mask; m; m &= m - 1) {
+                const int L = lowest(m);
+                const float hx = rdl(ax, L), hy = rdl(ay, L), hz = rdl(az, L), hb = rdl(b, L);
+                const float an1 = fabsf(hx) + fabsf(hy) + fabsf(hz), hs = rdl(sb, L);
+                bool o = false;
+#pragma unroll
+                for (int k = 0; k < kBatch; ++k) {
+                    const float sv = fmaf(hx, v.a[k], fmaf(hy, v.b[k], fmaf(hz, v.c[k], -hb)));
+                    const bool al = (v.al[k] >> ln) & 1;
+                    o |= al && (tol ? sv >= -64.f * kU * (an1 * e[k] + hs) : sv > 0.f);
+                }
+                if (o) cb |= 1ull << L;
+            }
+        }
+        uint64_t cut = wor64(cb);
+        if constexpr (G > 1) {
+            const uint32_t v2[2] = {(uint32_t)cut, (uint32_t)(cut >> 32)};
+            const uint32_t* t = exch(v2);
+            cut = 0;
+#pragma unroll
+            for (int w = 0; w < G; ++w) cut |= (uint64_t)t[w * 8] | ((uint64_t)t[w * 8 + 1] << 32);
+        }
+        return mask & cut;
+    }
+
     // Clips by the candidate sites of one leaf (those of lanes in `allow`);
     // nearest plane first.
     __device__ int leaf(uint32_t ref, uint64_t allow) {
@@ -1227,6 +1279,11 @@ struct Cell {
         };
         uint64_t mask = ballot(keep(cand));
         if constexpr (CAP > kHandoffCap) mask &= allow;
+        // wave groups drop the candidates that miss the cell all at once
+        // (not when every sign is taken in FP64)
+        if constexpr (G > 1) {
+            if (mask && robust < 2) mask = cutting(mask, ax, ay, az, b, 0.5f * (a2 + fabsf(dw)));
+        }
         while (mask) {
             int L;
             if (A.traversal == 2) {

@@ -11,7 +11,7 @@ namespace vd {
 
 constexpr int kMaxLeaf = 64;                 // leaf refs store count-1 in 6 bits
 constexpr int64_t kMaxSites = int64_t(1) << 25;  // leaf refs store `first` in 25 bits
-constexpr int kDefaultLeaf = 16;
+constexpr int kDefaultLeaf = 32;
 // Work distribution of the clip kernels: one contiguous range of cells per
 // XCD (workgroup b runs on XCD b % 8), taken kWorkChunk cells at a time.
 constexpr int kWorkRanges = 8;
