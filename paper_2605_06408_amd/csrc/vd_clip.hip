@@ -1201,8 +1201,9 @@ struct Cell {
     // some vertex of the cell outside, or, when doubtful signs are
     // re-evaluated, within rounding of it.  A plane that misses the cell
     // misses every cell it is later clipped to, so the others need no clip:
-    // for a wave group this is one pass and one exchange for the whole leaf
-    // instead of one clip each.  The test is the FP32 side test of classify.
+    // one pass over the vertices for the whole leaf (and for a wave group one
+    // exchange) instead of a selection and a clip each.  The test is the FP32
+    // side test of classify.
     __device__ uint64_t cutting(uint64_t mask, float ax, float ay, float az, float b, float sb) {
         const int ns = nsv();
         int lo, hi;
@@ -1279,9 +1280,9 @@ struct Cell {
         };
         uint64_t mask = ballot(keep(cand));
         if constexpr (CAP > kHandoffCap) mask &= allow;
-        // wave groups drop the candidates that miss the cell all at once
-        // (not when every sign is taken in FP64)
-        if constexpr (G > 1) {
+        // from 256 vertices up, the candidates that miss the cell are dropped
+        // all at once (not when every sign is taken in FP64)
+        if constexpr (G > 1 || VPL == 4) {
             if (mask && robust < 2) mask = cutting(mask, ax, ay, az, b, 0.5f * (a2 + fabsf(dw)));
         }
         while (mask) {
