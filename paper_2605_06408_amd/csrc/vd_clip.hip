@@ -47,6 +47,18 @@ namespace {
 constexpr float kU = 5.9604645e-08f;  // FP32 unit roundoff 2^-24
 constexpr double kU64 = 1.1102230246251565e-16;
 
+// The launch arguments seen through a pointer the compiler cannot keep
+// constant: the fields used once per cell (outputs, lists, counters) are then
+// loaded where they are used instead of being held in scalar registers
+// across the hot loops, which otherwise run out of them and spill.  Every
+// clip kernel takes its ClipArgs as the first kernel argument.
+using KArgs = const __attribute__((address_space(4))) ClipArgs;
+__device__ __forceinline__ KArgs* cold_args() {
+    KArgs* p = (KArgs*)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(p));
+    return p;
+}
+
 enum ClipResult { kNone = 0, kChanged = 1, kEmptied = 2, kOverflow = 3, kRestart = 4 };
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
@@ -1524,9 +1536,10 @@ struct Cell {
         const int F = np;
         const int ns = nsv();
         // facet order: ascending output code (box faces -6..-1, then original site ids)
+        const uint32_t* order = cold_args()->order;
         for (int q = ln; q < F; q += 64) {
             int32_t c = M.pcode[q];
-            M.key[q] = c >= 0 ? (int32_t)A.order[c] : c;
+            M.key[q] = c >= 0 ? (int32_t)order[c] : c;
         }
         wsync();
         for (int q = ln; q < F; q += 64) {
@@ -1537,7 +1550,16 @@ struct Cell {
             M.tb[q] = 0;
             M.anchor[q] = 0xFFFFFFFFu;
         }
-        const Stage& st = A.stage;
+        Stage st;
+        {
+            KArgs* ka = cold_args();
+            st.cap = ka->stage.cap;
+            st.vert = ka->stage.vert;
+            st.tri64 = ka->stage.tri64;
+            st.code = ka->stage.code;
+            st.fsize = ka->stage.fsize;
+            st.fv = ka->stage.fv;
+        }
         int32_t* codes = st.code + (int64_t)slot * st.cap;
         for (int q = ln; q < F; q += 64) codes[M.ta[q]] = M.key[q];
         // vertex renumbering 0..nv-1 (slot-major)
@@ -1679,31 +1701,33 @@ struct Cell {
         nbox = wsum_u(nbox);
         count(kCtrFinal, nv);
         if (ln == 0) {
-            A.cnt_v[orig] = nv;
-            A.cnt_f[orig] = (uint32_t)F;
-            A.cnt_n[orig] = (uint32_t)F - nbox;
-            A.vol[orig] = (float)(vol6 / 6.0);
+            KArgs* ka = cold_args();
+            ka->cnt_v[orig] = nv;
+            ka->cnt_f[orig] = (uint32_t)F;
+            ka->cnt_n[orig] = (uint32_t)F - nbox;
+            ka->vol[orig] = (float)(vol6 / 6.0);
             double inv = vol6 != 0.0 ? 0.25 / vol6 : 0.0;
-            A.cen[3 * orig] = (float)(p64[0] + ref[0] + mx * inv);
-            A.cen[3 * orig + 1] = (float)(p64[1] + ref[1] + my * inv);
-            A.cen[3 * orig + 2] = (float)(p64[2] + ref[2] + mz * inv);
-            A.flags[orig] = (uint8_t)flags;
-            A.loc[self] = make_loc((uint32_t)A.tier, slot);
+            ka->cen[3 * orig] = (float)(p64[0] + ref[0] + mx * inv);
+            ka->cen[3 * orig + 1] = (float)(p64[1] + ref[1] + my * inv);
+            ka->cen[3 * orig + 2] = (float)(p64[2] + ref[2] + mz * inv);
+            ka->flags[orig] = (uint8_t)flags;
+            ka->loc[self] = make_loc((uint32_t)A.tier, slot);
         }
         return true;
     }
 
     __device__ void write_empty(uint32_t orig, uint32_t extra) {
         if (ln == 0 && lead()) {
-            A.cnt_v[orig] = 0;
-            A.cnt_f[orig] = 0;
-            A.cnt_n[orig] = 0;
-            A.vol[orig] = 0.f;
-            A.cen[3 * orig] = px;
-            A.cen[3 * orig + 1] = py;
-            A.cen[3 * orig + 2] = pz;
-            A.flags[orig] = (uint8_t)(flags | kFlagEmpty | extra);
-            A.loc[self] = make_loc((uint32_t)A.tier, 0);
+            KArgs* ka = cold_args();
+            ka->cnt_v[orig] = 0;
+            ka->cnt_f[orig] = 0;
+            ka->cnt_n[orig] = 0;
+            ka->vol[orig] = 0.f;
+            ka->cen[3 * orig] = px;
+            ka->cen[3 * orig + 1] = py;
+            ka->cen[3 * orig + 2] = pz;
+            ka->flags[orig] = (uint8_t)(flags | kFlagEmpty | extra);
+            ka->loc[self] = make_loc((uint32_t)A.tier, 0);
         }
     }
 };
@@ -1713,7 +1737,8 @@ struct Cell {
 template <int VPL, bool kLds, bool kCount, int G = 1>
 __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
     Cell<VPL, kLds, kCount, G> C(M, A, gx);
-    const uint32_t count = A.list ? *A.list_count : (uint32_t)A.n;
+    KArgs* ka = cold_args();
+    const uint32_t count = ka->list ? *ka->list_count : (uint32_t)A.n;
     unsigned long long st_empty = 0, st_large = 0, st_unc = 0, st_fail = 0, st_fp64 = 0, st_res = 0;
     // Cells are split into kWorkRanges contiguous (Morton-ordered) ranges, one
     // per XCD: the waves of workgroup b take chunks of their own range b % 8
@@ -1729,7 +1754,7 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
                 const uint32_t lo = (uint32_t)((uint64_t)count * r / kWorkRanges);
                 const uint32_t hi = (uint32_t)((uint64_t)count * (r + 1) / kWorkRanges);
                 uint32_t c0 = 0;
-                if (C.ln == 0 && C.lead()) c0 = atomicAdd(&A.work_counter[r], (uint32_t)kWorkChunk);
+                if (C.ln == 0 && C.lead()) c0 = atomicAdd(&cold_args()->work_counter[r], (uint32_t)kWorkChunk);
                 c0 = C.bcast(c0);
                 if (c0 < hi - lo) {
                     cur = lo + c0;
@@ -1743,13 +1768,14 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
             if (!got) break;
         }
         const uint32_t c = cur++;
-        const uint32_t k = A.list ? A.list[c] : c;
-        const uint32_t slot = A.list ? c : k;
-        const uint32_t orig = A.order[k];
+        KArgs* kc = cold_args();
+        const uint32_t k = kc->list ? kc->list[c] : c;
+        const uint32_t slot = kc->list ? c : k;
+        const uint32_t orig = kc->order[k];
         // a cell the previous pass handed over goes on from where it stopped
         const Handoff* hin = nullptr;
         if constexpr (Tier<VPL>::CAP > kHandoffCap)
-            if (A.handoff && c < A.handoff_cap && A.handoff[c].valid) hin = &A.handoff[c];
+            if (kc->handoff && c < kc->handoff_cap && kc->handoff[c].valid) hin = &kc->handoff[c];
         // a cell is built with plain FP32 signs first (mixed mode: with FP64
         // re-evaluation of doubtful ones); if that meets an inconsistent
         // configuration it is rebuilt with the FP64 re-evaluation, then with
@@ -1775,15 +1801,16 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
                 continue;
             }
             if (r == kOverflow) {
-                if (A.next_list) {
+                KArgs* kn = cold_args();
+                if (kn->next_list) {
                     uint32_t pos = 0;
                     if (C.ln == 0 && C.lead()) {
-                        pos = atomicAdd(A.next_count, 1u);
-                        A.next_list[pos] = k;
+                        pos = atomicAdd(kn->next_count, 1u);
+                        kn->next_list[pos] = k;
                     }
                     if constexpr (Tier<VPL>::CAP == kHandoffCap) {
                         pos = C.bcast(pos);
-                        if (A.handoff && pos < A.handoff_cap) C.save(A.handoff[pos]);
+                        if (kn->handoff && pos < kn->handoff_cap) C.save(kn->handoff[pos]);
                     }
                     escalated = true;
                 } else {
@@ -1828,15 +1855,16 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
         st_fp64 += (C.flags & kFlagFP64) ? 1 : 0;
     }
     if (C.ln == 0 && C.lead()) {
+        ka = cold_args();
         if constexpr (kCount)
             for (int c = 0; c < kCtrCount; ++c)
-                if (C.ctr[c]) atomicAdd(&A.ctr[c], (unsigned long long)C.ctr[c]);
-        if (st_empty) atomicAdd(&A.stats[kStatEmpty], st_empty);
-        if (st_large) atomicAdd(&A.stats[kStatLarge], st_large);
-        if (st_unc) atomicAdd(&A.stats[kStatUncertain], st_unc);
-        if (st_fail) atomicAdd(&A.stats[kStatFailed], st_fail);
-        if (st_fp64) atomicAdd(&A.stats[kStatFP64], st_fp64);
-        if (st_res) atomicAdd(&A.stats[kStatResumed], st_res);
+                if (C.ctr[c]) atomicAdd(&ka->ctr[c], (unsigned long long)C.ctr[c]);
+        if (st_empty) atomicAdd(&ka->stats[kStatEmpty], st_empty);
+        if (st_large) atomicAdd(&ka->stats[kStatLarge], st_large);
+        if (st_unc) atomicAdd(&ka->stats[kStatUncertain], st_unc);
+        if (st_fail) atomicAdd(&ka->stats[kStatFailed], st_fail);
+        if (st_fp64) atomicAdd(&ka->stats[kStatFP64], st_fp64);
+        if (st_res) atomicAdd(&ka->stats[kStatResumed], st_res);
     }
 }
 
