@@ -79,41 +79,58 @@ __device__ __forceinline__ uint32_t uni(uint32_t v) { return (uint32_t)__builtin
 // (quad_perm [1,0,3,2] and [2,3,0,1]), across half-rows and rows
 // (row_half_mirror, row_mirror), then row 0 into 1 and 2 into 3
 // (row_bcast:15) and rows 0-1 into 2-3 (row_bcast:31); lane 63 holds the
-// result, which is returned to every lane.  Lanes of rows a step does not
-// write keep `keep` (the operand's identity for sums, the value itself for
-// min and max).  All 64 lanes must be active.
+// result, which is returned to every lane.  All 64 lanes must be active.
+// dpp: lanes of rows the move does not write get `keep` (the identity of
+// the sum it feeds).
 template <int kCtrl, int kRows>
 __device__ __forceinline__ int dpp(int keep, int v) {
     return __builtin_amdgcn_update_dpp(keep, v, kCtrl, kRows, 0xF, false);
 }
+// A move within rows (every lane reads a lane of its own row, so all reads
+// are valid): the compiler can fold it into the operation that uses it.
+template <int kCtrl>
+__device__ __forceinline__ int dpp_row(int v) {
+    return __builtin_amdgcn_mov_dpp(v, kCtrl, 0xF, 0xF, true);
+}
+// The two row broadcasts write only rows 1, 3 and then 2, 3; what the
+// other rows then hold never reaches lane 63, so they need no defined value.
+template <int kCtrl, int kRows>
+__device__ __forceinline__ int dpp_bcast(int v) {
+    return __builtin_amdgcn_mov_dpp(v, kCtrl, kRows, 0xF, false);
+}
 template <typename Op>
-__device__ __forceinline__ int wave_reduce_i(int v, int zero, bool idem, Op op) {
-    v = op(v, dpp<0xB1, 0xF>(idem ? v : zero, v));
-    v = op(v, dpp<0x4E, 0xF>(idem ? v : zero, v));
-    v = op(v, dpp<0x141, 0xF>(idem ? v : zero, v));
-    v = op(v, dpp<0x140, 0xF>(idem ? v : zero, v));
-    v = op(v, dpp<0x142, 0xA>(idem ? v : zero, v));
-    v = op(v, dpp<0x143, 0xC>(idem ? v : zero, v));
+__device__ __forceinline__ int wave_reduce_i(int v, Op op) {
+    v = op(v, dpp_row<0xB1>(v));
+    v = op(v, dpp_row<0x4E>(v));
+    v = op(v, dpp_row<0x141>(v));
+    v = op(v, dpp_row<0x140>(v));
+    v = op(v, dpp_bcast<0x142, 0xA>(v));
+    v = op(v, dpp_bcast<0x143, 0xC>(v));
     return __builtin_amdgcn_readlane(v, 63);
 }
+// Float min and max reduce as integers: the bits of a float with the
+// magnitude bits of negative values flipped order like the values (NaN is
+// never reduced), so each step is one integer min or max on a lane move,
+// with no float canonicalisation between the steps.
+__device__ __forceinline__ int ford(float f) {
+    const int i = __float_as_int(f);
+    return i ^ ((i >> 31) & 0x7FFFFFFF);
+}
+__device__ __forceinline__ float unford(int k) { return __int_as_float(k ^ ((k >> 31) & 0x7FFFFFFF)); }
 __device__ __forceinline__ float wmin(float v) {
-    return __int_as_float(wave_reduce_i(__float_as_int(v), 0, true, [](int a, int b) {
-        return __float_as_int(fminf(__int_as_float(a), __int_as_float(b)));
-    }));
+    return unford(wave_reduce_i(ford(v), [](int a, int b) { return min(a, b); }));
 }
 __device__ __forceinline__ float wmax(float v) {
-    return __int_as_float(wave_reduce_i(__float_as_int(v), 0, true, [](int a, int b) {
-        return __float_as_int(fmaxf(__int_as_float(a), __int_as_float(b)));
-    }));
+    return unford(wave_reduce_i(ford(v), [](int a, int b) { return max(a, b); }));
 }
 __device__ __forceinline__ uint64_t wor64(uint64_t v) {
     auto op = [](int a, int b) { return a | b; };
-    const uint32_t lo = (uint32_t)wave_reduce_i((int)(uint32_t)v, 0, true, op);
-    const uint32_t hi = (uint32_t)wave_reduce_i((int)(uint32_t)(v >> 32), 0, true, op);
+    const uint32_t lo = (uint32_t)wave_reduce_i((int)(uint32_t)v, op);
+    const uint32_t hi = (uint32_t)wave_reduce_i((int)(uint32_t)(v >> 32), op);
     return (uint64_t)lo | ((uint64_t)hi << 32);
 }
 __device__ __forceinline__ uint32_t wsum_u(uint32_t v) {
-    return (uint32_t)wave_reduce_i((int)v, 0, false, [](int a, int b) { return (int)((uint32_t)a + (uint32_t)b); });
+    return (uint32_t)wave_reduce_i((int)v, [](int a, int b) { return (int)((uint32_t)a + (uint32_t)b); });
 }
 template <int kCtrl, int kRows>
 __device__ __forceinline__ double dpp64(double v) {
@@ -908,7 +925,6 @@ struct Cell {
                 vt[s] = T::pack3(h, x, y);
                 va[s] = T::pack3(T::fld(r, 0), nb1[s], nb2[s]);
                 float4 P = M.pl[x], Q = M.pl[y];
-                float sbx = M.psb[x], sby = M.psb[y];
                 // n0 = a_x cross a_y, n1 = a_y cross a_h, n2 = a_h cross a_x
                 float n00 = P.y * Q.z - P.z * Q.y, n01 = P.z * Q.x - P.x * Q.z, n02 = P.x * Q.y - P.y * Q.x;
                 float n10 = Q.y * az - Q.z * ay, n11 = Q.z * ax - Q.x * az, n12 = Q.x * ay - Q.y * ax;
@@ -921,9 +937,15 @@ struct Cell {
                 y0[s] = q0;
                 y1[s] = q1;
                 y2[s] = q2;
-                float e = (sbh * (fabsf(n00) + fabsf(n01) + fabsf(n02)) + sbx * (fabsf(n10) + fabsf(n11) + fabsf(n12)) +
-                           sby * (fabsf(n20) + fabsf(n21) + fabsf(n22))) * fabsf(inv);
-                ev[s] = e + fabsf(q0) + fabsf(q1) + fabsf(q2);
+                // error scale of the vertex, for the doubtful-sign test (only
+                // read when signs are checked: robust builds)
+                if (robust != 0) {
+                    const float sbx = M.psb[x], sby = M.psb[y];
+                    float e = (sbh * (fabsf(n00) + fabsf(n01) + fabsf(n02)) +
+                               sbx * (fabsf(n10) + fabsf(n11) + fabsf(n12)) +
+                               sby * (fabsf(n20) + fabsf(n21) + fabsf(n22))) * fabsf(inv);
+                    ev[s] = e + fabsf(q0) + fabsf(q1) + fabsf(q2);
+                }
             }
         }
 #pragma unroll
