@@ -930,7 +930,9 @@ struct Cell {
                 float n10 = Q.y * az - Q.z * ay, n11 = Q.z * ax - Q.x * az, n12 = Q.x * ay - Q.y * ax;
                 float n20 = ay * P.z - az * P.y, n21 = az * P.x - ax * P.z, n22 = ax * P.y - ay * P.x;
                 float det = fmaf(ax, n00, fmaf(ay, n01, az * n02));
-                float inv = 1.0f / det;
+                // hardware reciprocal (1 ulp): the FP32 position only decides
+                // signs, within the error scale; outputs are recomputed in FP64
+                float inv = __builtin_amdgcn_rcpf(det);
                 const float q0 = (b * n00 + P.w * n10 + Q.w * n20) * inv;
                 const float q1 = (b * n01 + P.w * n11 + Q.w * n21) * inv;
                 const float q2 = (b * n02 + P.w * n12 + Q.w * n22) * inv;
@@ -1102,7 +1104,7 @@ struct Cell {
             const float dfar = sqrtf(fmaf(fx, fx, fmaf(fy, fy, fz * fz)));
             const float dc = fminf(fmaxf(sqrtf(dw), d), dfar);
             if (dc > 0.f) {
-                lb = 0.5f * dc + 0.5f * dw / dc;
+                lb = 0.5f * dc + 0.5f * dw * __builtin_amdgcn_rcpf(dc);
                 err = lb;
             } else {
                 lb = 0.5f * d;
@@ -1112,8 +1114,9 @@ struct Cell {
             lb = 0.5f * d;
             err = 0.5f * d;
         } else if (d > 0.f) {
-            lb = 0.5f * d + 0.5f * dw / d;
-            err = 0.5f * d - 0.5f * dw / d;
+            const float q = 0.5f * dw * __builtin_amdgcn_rcpf(d);
+            lb = 0.5f * d + q;
+            err = 0.5f * d - q;
         } else {
             lb = -INFINITY;
             err = 0.f;
