@@ -1091,7 +1091,8 @@ struct Cell {
         float blx = c.lo[0] - px, bly = c.lo[1] - py, blz = c.lo[2] - pz;
         float bhx = c.hi[0] - px, bhy = c.hi[1] - py, bhz = c.hi[2] - pz;
         float dx = fmaxf(fmaxf(blx, -bhx), 0.f), dy = fmaxf(fmaxf(bly, -bhy), 0.f), dz = fmaxf(fmaxf(blz, -bhz), 0.f);
-        float d = sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
+        // hardware square roots (1 ulp), inside the bound's rounding margin
+        float d = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
         float dw = pw - c.wmax;
         float lb, err;
         if (dw > 0.f && A.culling == 3) {
@@ -1101,8 +1102,8 @@ struct Cell {
             // that range (the paper's bound keeps only dw < 0 and is d/2 here)
             const float fx = fmaxf(fabsf(blx), fabsf(bhx)), fy = fmaxf(fabsf(bly), fabsf(bhy)),
                         fz = fmaxf(fabsf(blz), fabsf(bhz));
-            const float dfar = sqrtf(fmaf(fx, fx, fmaf(fy, fy, fz * fz)));
-            const float dc = fminf(fmaxf(sqrtf(dw), d), dfar);
+            const float dfar = __builtin_amdgcn_sqrtf(fmaf(fx, fx, fmaf(fy, fy, fz * fz)));
+            const float dc = fminf(fmaxf(__builtin_amdgcn_sqrtf(dw), d), dfar);
             if (dc > 0.f) {
                 lb = 0.5f * dc + 0.5f * dw * __builtin_amdgcn_rcpf(dc);
                 err = lb;
@@ -1130,7 +1131,7 @@ struct Cell {
             float tz = bhz >= 0.f ? (blz < 0.f ? fmaxf(hz2, lz2) : hz2) : lz2;
             rb2 = tx + ty + tz;
         }
-        float rb = sqrtf(rb2);
+        float rb = __builtin_amdgcn_sqrtf(rb2);
         // lower bound made safe against FP32 rounding of its terms
         float lbs = lb - 16.f * kU * err;
         *key = lbs;
@@ -1299,7 +1300,7 @@ struct Cell {
                 dw = pw - q.w;
                 b = 0.5f * (a2 + dw);
                 cand = a2 > 0.f;
-                key = b * rsqrtf(a2);
+                key = b * __builtin_amdgcn_rsqf(a2);  // orders candidates only
             }
         }
         auto keep = [&](bool c) -> bool {
@@ -1427,7 +1428,7 @@ struct Cell {
                 float k;
                 pop(&e, &k);
                 count(kCtrNode, 1);
-                if (A.traversal != 2 && k > sqrtf(rmax2) * (1.f + 16.f * kU)) {
+                if (A.traversal != 2 && k > __builtin_amdgcn_sqrtf(rmax2) * (1.f + 16.f * kU)) {
                     qn = 0;  // every key left is at least k: nothing can cut the cell
                     break;
                 }
