@@ -117,6 +117,10 @@ __device__ __forceinline__ int ford(float f) {
     return i ^ ((i >> 31) & 0x7FFFFFFF);
 }
 __device__ __forceinline__ float unford(int k) { return __int_as_float(k ^ ((k >> 31) & 0x7FFFFFFF)); }
+// Maximum of two non-negative floats (their bits order like integers).
+__device__ __forceinline__ float pmax(float a, float b) {
+    return __int_as_float(max(__float_as_int(a), __float_as_int(b)));
+}
 __device__ __forceinline__ float wmin(float v) {
     return unford(wave_reduce_i(ford(v), [](int a, int b) { return min(a, b); }));
 }
@@ -1100,8 +1104,8 @@ struct Cell {
             // f(t) = t/2 + dw/(2t), and |a_j| lies between the box's nearest
             // and farthest distances: the bound is f at sqrt(dw) clamped to
             // that range (the paper's bound keeps only dw < 0 and is d/2 here)
-            const float fx = fmaxf(fabsf(blx), fabsf(bhx)), fy = fmaxf(fabsf(bly), fabsf(bhy)),
-                        fz = fmaxf(fabsf(blz), fabsf(bhz));
+            const float fx = pmax(fabsf(blx), fabsf(bhx)), fy = pmax(fabsf(bly), fabsf(bhy)),
+                        fz = pmax(fabsf(blz), fabsf(bhz));
             const float dfar = __builtin_amdgcn_sqrtf(fmaf(fx, fx, fmaf(fy, fy, fz * fz)));
             const float dc = fminf(fmaxf(__builtin_amdgcn_sqrtf(dw), d), dfar);
             if (dc > 0.f) {
@@ -1126,9 +1130,10 @@ struct Cell {
         if (A.culling == 2) {
             rb2 = riso2;
         } else {
-            float tx = bhx >= 0.f ? (blx < 0.f ? fmaxf(hx2, lx2) : hx2) : lx2;
-            float ty = bhy >= 0.f ? (bly < 0.f ? fmaxf(hy2, ly2) : hy2) : ly2;
-            float tz = bhz >= 0.f ? (blz < 0.f ? fmaxf(hz2, lz2) : hz2) : lz2;
+            // per axis: the far-corner square of each side the box reaches
+            const float tx = pmax(bhx >= 0.f ? hx2 : 0.f, blx < 0.f ? lx2 : 0.f);
+            const float ty = pmax(bhy >= 0.f ? hy2 : 0.f, bly < 0.f ? ly2 : 0.f);
+            const float tz = pmax(bhz >= 0.f ? hz2 : 0.f, blz < 0.f ? lz2 : 0.f);
             rb2 = tx + ty + tz;
         }
         float rb = __builtin_amdgcn_sqrtf(rb2);
