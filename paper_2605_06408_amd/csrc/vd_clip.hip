@@ -583,6 +583,56 @@ struct Cell {
         return g_or(ballot(hit) != 0);
     }
 
+    // The ball test of both child records (lanes 0 and 1) in one pass over
+    // the vertices (the vertex's own power is shared by the two boxes).
+    __device__ void ball_hit_pair(const NodeChild& c, bool* hit0, bool* hit1) {
+        if constexpr (kCount) count(kCtrBall, 2 * nalive());
+        const float blx = c.lo[0] - px, bly = c.lo[1] - py, blz = c.lo[2] - pz;
+        const float bhx = c.hi[0] - px, bhy = c.hi[1] - py, bhz = c.hi[2] - pz;
+        const float l0x = rdl(blx, 0), l0y = rdl(bly, 0), l0z = rdl(blz, 0);
+        const float h0x = rdl(bhx, 0), h0y = rdl(bhy, 0), h0z = rdl(bhz, 0), w0 = rdl(c.wmax, 0);
+        const float l1x = rdl(blx, 1), l1y = rdl(bly, 1), l1z = rdl(blz, 1);
+        const float h1x = rdl(bhx, 1), h1y = rdl(bhy, 1), h1z = rdl(bhz, 1), w1 = rdl(c.wmax, 1);
+        bool a0 = false, a1 = false;
+        const int ns = nsv();
+        int lo, hi;
+        share(ns, kBatch, &lo, &hi);
+        for (int s0 = (kReg ? 0 : lo); s0 < (kReg ? VPL : hi); s0 += kBatch) {
+            VBatch v;
+            load_batch(s0, ns, v);
+#pragma unroll
+            for (int k = 0; k < kBatch; ++k) {
+                if ((v.al[k] >> ln) & 1) {
+                    const float a = v.a[k], b = v.b[k], cc = v.c[k];
+                    const float r2 = fmaf(a, a, fmaf(b, b, cc * cc)), rhs = r2 - pw, tol = r2 + fabsf(pw);
+                    float dx = fmaxf(fmaxf(l0x - a, a - h0x), 0.f);
+                    float dy = fmaxf(fmaxf(l0y - b, b - h0y), 0.f);
+                    float dz = fmaxf(fmaxf(l0z - cc, cc - h0z), 0.f);
+                    float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    a0 |= (d2 - w0) - rhs <= 16.f * kU * (d2 + tol + fabsf(w0));
+                    dx = fmaxf(fmaxf(l1x - a, a - h1x), 0.f);
+                    dy = fmaxf(fmaxf(l1y - b, b - h1y), 0.f);
+                    dz = fmaxf(fmaxf(l1z - cc, cc - h1z), 0.f);
+                    d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                    a1 |= (d2 - w1) - rhs <= 16.f * kU * (d2 + tol + fabsf(w1));
+                }
+            }
+        }
+        bool r0 = ballot(a0) != 0, r1 = ballot(a1) != 0;
+        if constexpr (G > 1) {
+            const uint32_t v2[2] = {r0 ? 1u : 0u, r1 ? 1u : 0u};
+            const uint32_t* t = exch(v2);
+            r0 = r1 = false;
+#pragma unroll
+            for (int w = 0; w < G; ++w) {
+                r0 |= t[w * 8] != 0;
+                r1 |= t[w * 8 + 1] != 0;
+            }
+        }
+        *hit0 = r0;
+        *hit1 = r1;
+    }
+
     // Applies the ball test to the child record held by lane `l`.
     __device__ bool ball_hit_lane(const NodeChild& c, int l) {
         float lx = rdl(c.lo[0] - px, l), ly = rdl(c.lo[1] - py, l), lz = rdl(c.lo[2] - pz, l);
@@ -1401,8 +1451,15 @@ struct Cell {
                 }
                 bool c0 = rdl((int)cull, 0) != 0, c1 = rdl((int)cull, 1) != 0;
                 if (A.culling == 3) {
-                    if (!c0 && !ball_hit_lane(cc, 0)) c0 = true;
-                    if (!c1 && !ball_hit_lane(cc, 1)) c1 = true;
+                    if (!c0 && !c1) {
+                        bool h0, h1;
+                        ball_hit_pair(cc, &h0, &h1);
+                        c0 = !h0;
+                        c1 = !h1;
+                    } else {
+                        if (!c0 && !ball_hit_lane(cc, 0)) c0 = true;
+                        if (!c1 && !ball_hit_lane(cc, 1)) c1 = true;
+                    }
                 }
                 if (c0 && c1) {
                     have = false;
