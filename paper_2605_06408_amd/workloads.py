@@ -24,6 +24,17 @@ paper stresses -- uniform, strongly clustered, surface-like and weighted):
                      far field in [-4.5, 5.5]^3 (the 10x box); box = that box
   power_clustered    clustered positions (same seed) with the power_uniform
                      weight law at s = 0.005
+
+The paper's own synthetic sets (Sec. 5.1), all in Omega = [-10, 10]^3, box
+Omega:
+
+  paper_uniform      p ~ U(Omega)
+  paper_clusters     K cluster centres U(Omega), points split evenly over the
+                     clusters, N(c, 0.1^2 I), clamped to Omega (K = 5 or 10)
+  paper_gradient     density linear in x: x = a + (b - a) sqrt(u), u ~ U(0,1),
+                     y, z ~ U(a, b), [a, b] = [-10, 10]
+  paper_*_w          the same positions with w ~ N(0, (d_nn^2 / 3)^2), d_nn the
+                     median nearest-neighbour distance of the set
 """
 from __future__ import annotations
 
@@ -132,7 +143,57 @@ def surface(n: int, seed: int = 0, n_shapes: int = 500, far: float = 0.05, offse
     return xyz, None, BIG_BOX.copy()
 
 
-# The five benchmark configurations at their full sizes.
+PAPER_BOX = np.array([-10.0, -10.0, -10.0, 10.0, 10.0, 10.0])
+
+
+def paper_uniform(n: int, seed: int = 0):
+    rng = np.random.default_rng(seed)
+    xyz = (-10.0 + 20.0 * rng.random((n, 3))).astype(np.float32)
+    return xyz, None, PAPER_BOX.copy()
+
+
+def paper_clusters(n: int, seed: int = 0, k: int = 10, sigma: float = 0.1):
+    rng = np.random.default_rng(seed)
+    centres = -10.0 + 20.0 * rng.random((k, 3))
+    base, extra = divmod(n, k)
+    parts = [rng.normal(centres[j], sigma, size=(base + (1 if j < extra else 0), 3)) for j in range(k)]
+    xyz = np.clip(np.concatenate(parts), -10.0, 10.0).astype(np.float32)
+    return xyz, None, PAPER_BOX.copy()
+
+
+def paper_gradient(n: int, seed: int = 0):
+    rng = np.random.default_rng(seed)
+    a, b = -10.0, 10.0
+    x = a + (b - a) * np.sqrt(rng.random(n))
+    yz = a + (b - a) * rng.random((n, 2))
+    xyz = np.column_stack([x, yz]).astype(np.float32)
+    return xyz, None, PAPER_BOX.copy()
+
+
+def paper_weights(xyz, seed: int = 0):
+    """w ~ N(0, (d_nn^2 / 3)^2) with d_nn the median nearest-neighbour
+    distance of the (FP32) sites."""
+    from scipy.spatial import cKDTree
+    p = np.asarray(xyz, np.float64)
+    d, _ = cKDTree(p).query(p, k=2, workers=-1)
+    dnn = float(np.median(d[:, 1]))
+    rng = np.random.default_rng(seed + 2_000_003)
+    return rng.normal(0.0, dnn * dnn / 3.0, size=len(p)).astype(np.float32)
+
+
+def _weighted(gen):
+    def fn(n: int, seed: int = 0):
+        xyz, _, box = gen(n, seed)
+        return xyz, paper_weights(xyz, seed), box
+    return fn
+
+
+def _clusters(k: int):
+    return lambda n, seed=0: paper_clusters(n, seed, k)
+
+
+# The five benchmark configurations at their full sizes, then the paper's
+# own synthetic sets at 1M and 15M sites.
 CONFIGS = {
     "uniform_10k": (uniform, 10_000),
     "clustered_1m": (clustered, 1_000_000),
@@ -140,6 +201,11 @@ CONFIGS = {
     "surface_20m": (surface, 20_000_000),
     "power_clustered_1m": (power_clustered, 1_000_000),
 }
+for _n, _tag in ((1_000_000, "1m"), (15_000_000, "15m")):
+    for _name, _gen in (("paper_uniform", paper_uniform), ("paper_gradient", paper_gradient),
+                        ("paper_clusters5", _clusters(5)), ("paper_clusters10", _clusters(10))):
+        CONFIGS["%s_%s" % (_name, _tag)] = (_gen, _n)
+        CONFIGS["%s_w_%s" % (_name, _tag)] = (_weighted(_gen), _n)
 
 
 def make(name: str, seed: int = 0, n: int | None = None):

@@ -64,6 +64,15 @@ def test_power_clustered_small(oracle_mod):
     _full_parity(oracle_mod, xyz, w, box, min_frac=0.85)
 
 
+@pytest.mark.parametrize("name", ["paper_uniform", "paper_gradient", "paper_clusters5", "paper_clusters10"])
+@pytest.mark.parametrize("weighted", [False, True], ids=["voronoi", "power"])
+def test_paper_synthetic_sets(oracle_mod, name, weighted):
+    # the paper's own synthetic sets (Sec. 5.1) at 20k sites, whole diagrams
+    xyz, w, box = wl.make("%s%s_1m" % (name, "_w" if weighted else ""), 11, 20000)
+    assert (w is not None) == weighted
+    _full_parity(oracle_mod, xyz, w, box, min_frac=0.9)
+
+
 @pytest.mark.parametrize("n", [1, 2, 3, 15, 16, 17, 63, 64, 65, 1000, 4097])
 def test_ragged_sizes(oracle_mod, n):
     xyz, w, box = wl.uniform(n, 100 + n)
