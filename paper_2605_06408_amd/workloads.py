@@ -6,10 +6,9 @@ Every generator draws in FP64 with ``numpy.random.default_rng(seed)`` (PCG64)
 and casts to FP32 at the end.  Each returns ``(xyz f32[n,3], w f32[n] or
 None, box f64[6])`` with box = [xmin, ymin, zmin, xmax, ymax, zmax].
 
-Workloads (the paper's own sets are uniform, Gaussian-cluster and
-density-gradient clouds in [-10, 10]^3 plus Radiant Foam checkpoints, none of
-which ship here; these synthetic stand-ins reproduce the distributions the
-paper stresses -- uniform, strongly clustered, surface-like and weighted):
+Benchmark workloads (synthetic stand-ins for the distributions the paper
+stresses -- uniform, strongly clustered, surface-like and weighted; its
+Radiant Foam checkpoints do not ship here):
 
   uniform            n sites U[0,1]^3, Voronoi, box [0,1]^3
   clustered          10% U[0,1]^3 background + 90% over 64 isotropic Gaussian
