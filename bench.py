@@ -73,13 +73,17 @@ def parse():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--config", default="clustered_1m",
-                    help="uniform_10k | clustered_1m | power_uniform_1m | surface_20m | power_clustered_1m")
+                    help="uniform_10k | clustered_1m | power_uniform_1m | surface_20m | power_clustered_1m, "
+                         "or one of the paper's sets, paper_{uniform,gradient,clusters5,clusters10}[_w]_{1m,15m}")
     ap.add_argument("--n", type=int, default=None, help="override the site count")
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--precision", type=int, default=1, help="1 fp32, 2 mixed fp32/fp64")
     ap.add_argument("--leaf-size", type=int, default=0)
     ap.add_argument("--culling", type=int, default=3)
     ap.add_argument("--traversal", type=int, default=1)
+    ap.add_argument("--weight-ratio", type=float, default=None,
+                    help="replace the weights by w ~ N(0, (ratio * d_nn)^2), d_nn the median "
+                         "nearest-neighbour distance (the paper's weight sweep)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-extra", action="store_true",
                     help="skip the mixed-precision and fwd+bwd legs")
@@ -204,6 +208,8 @@ def main():
 
     log("generating %s" % args.config)
     xyz, w, box = wl.make(args.config, args.seed, args.n)
+    if args.weight_ratio is not None:
+        w = wl.ratio_weights(xyz, args.seed, args.weight_ratio)
     n = len(xyz)
     log("generated n=%d" % n)
     if args.copy_calibration:
@@ -261,6 +267,7 @@ def main():
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": args.config, "n": n, "seed": args.seed, "box": bbox,
                    "weights": w is not None, "precision": "fp32" if args.precision == 1 else "mixed fp32/fp64",
+                   "weight_ratio": args.weight_ratio,
                    "leaf_size": args.leaf_size or 32, "culling": args.culling, "traversal": args.traversal},
         "roofline": roofline,
         "phases_ms": phases,

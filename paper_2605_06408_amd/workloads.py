@@ -169,15 +169,28 @@ def paper_gradient(n: int, seed: int = 0):
     return xyz, None, PAPER_BOX.copy()
 
 
-def paper_weights(xyz, seed: int = 0):
-    """w ~ N(0, (d_nn^2 / 3)^2) with d_nn the median nearest-neighbour
-    distance of the (FP32) sites."""
+def median_nn_distance(xyz) -> float:
     from scipy.spatial import cKDTree
     p = np.asarray(xyz, np.float64)
     d, _ = cKDTree(p).query(p, k=2, workers=-1)
-    dnn = float(np.median(d[:, 1]))
+    return float(np.median(d[:, 1]))
+
+
+def paper_weights(xyz, seed: int = 0):
+    """w ~ N(0, (d_nn^2 / 3)^2) with d_nn the median nearest-neighbour
+    distance of the (FP32) sites."""
+    dnn = median_nn_distance(xyz)
     rng = np.random.default_rng(seed + 2_000_003)
-    return rng.normal(0.0, dnn * dnn / 3.0, size=len(p)).astype(np.float32)
+    return rng.normal(0.0, dnn * dnn / 3.0, size=len(xyz)).astype(np.float32)
+
+
+def ratio_weights(xyz, seed: int, ratio: float):
+    """The paper's weight sweep (Sec. 5.2): w ~ N(0, sd^2) with sd the
+    median nearest-neighbour distance times `ratio` (taken as stated; ratio 0
+    gives w = 0, the Voronoi diagram)."""
+    sd = ratio * median_nn_distance(xyz) if ratio else 0.0
+    rng = np.random.default_rng(seed + 3_000_017)
+    return rng.normal(0.0, sd, size=len(xyz)).astype(np.float32) if sd else np.zeros(len(xyz), np.float32)
 
 
 def _weighted(gen):
