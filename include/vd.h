@@ -198,6 +198,21 @@ VD_API vd_status vd_write(vd_context* ctx, const vd_outputs* out, void* stream);
 VD_API vd_status vd_backward(vd_context* ctx, const float* g_vol, const float* g_cen, const float* g_vert,
                              float* g_xyz, float* g_w, void* stream);
 
+/* The dual of the last build (paper Sec. 3: the power diagram's dual is the
+ * regular triangulation of the weighted sites; for equal weights the Delaunay
+ * tetrahedralisation): one tetrahedron per diagram vertex that lies inside the
+ * box, i.e. whose three facets are all site facets -- that vertex joins the
+ * cells of four sites i < j < k < l, and the row is (i, j, k, l).  Tetrahedra
+ * whose vertex (their power centre) falls outside the box are not listed.
+ *   tets      device int32[capacity * 4] out, or NULL to only count
+ *   capacity  rows available in tets
+ *   count     HOST int64 out: the number of tetrahedra
+ * Rows are grouped by their smallest site i (ascending), then in the vertex
+ * order of that cell in vd_write.  Host-blocking (it synchronises `stream` to
+ * count); VD_ERR_INVALID_ARG if capacity is below the count (nothing
+ * written), VD_ERR_STATE without a build. */
+VD_API vd_status vd_tetrahedra(vd_context* ctx, int32_t* tets, int64_t capacity, int64_t* count, void* stream);
+
 /* Counters of the last build (see vd_sizes); host call, no device work. */
 VD_API vd_status vd_get_sizes(const vd_context* ctx, vd_sizes* sizes);
 

@@ -7,7 +7,8 @@ its Python binding) never imports it and shares no code with it.
 ``cells()`` wraps ``liboracle.so`` (``vd_oracle.cpp``: FP64 brute-force
 clipping of the cell definition, paper Sec. 3 Eq. 1 and Sec. 4.1).
 ``brute`` holds an exact-rational vertex enumeration used to pin the C++
-oracle on tiny inputs.
+oracle on tiny inputs.  ``tetrahedra()`` reads the dual (regular / Delaunay)
+tetrahedra off the cells.
 
 Output layout (canonical, per requested cell, CSR over the requested cells):
   nbr_off/nbr          neighbour site ids, ascending
@@ -129,6 +130,23 @@ def cells(xyz, w=None, box=None, ids=None, margin: bool = True, threads: int = 0
         lib.orc_free(h)
     out["ids"] = np.arange(n, dtype=np.int64) if ids is None else ids
     return out
+
+
+def tetrahedra(res: dict) -> np.ndarray:
+    """Dual tetrahedra listed by the requested cells of a ``cells()`` result
+    (paper Sec. 3: the power diagram's dual is the regular triangulation; with
+    equal weights the Delaunay tetrahedralisation).  A vertex of cell i whose
+    three planes are all site planes j < k < l with j > i is the power centre
+    of tetrahedron (i, j, k, l); box-face vertices have no dual tetrahedron.
+    Rows [T, 4] int64, sorted."""
+    rows = []
+    for t, i in enumerate(res["ids"]):
+        codes = res["vert_code"][res["vert_off"][t]:res["vert_off"][t + 1]]
+        for c in codes:
+            if c[0] > i:
+                rows.append((int(i), int(c[0]), int(c[1]), int(c[2])))
+    out = np.array(sorted(rows), dtype=np.int64)
+    return out.reshape(-1, 4)
 
 
 def cell_view(res: dict, t: int) -> dict:

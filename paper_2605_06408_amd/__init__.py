@@ -112,6 +112,8 @@ def load_library():
             lib.vd_get_counters.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32]
             lib.vd_backward.restype = ctypes.c_int
             lib.vd_backward.argtypes = [P, P, P, P, P, P, P]
+            lib.vd_tetrahedra.restype = ctypes.c_int
+            lib.vd_tetrahedra.argtypes = [P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P]
             _lib = lib
     return _lib
 
@@ -230,6 +232,22 @@ class Context:
     def build(self, xyz, w=None, bbox=None, **kw) -> Diagram:
         sz = self.build_sizes(xyz, w, bbox, **kw)
         return self.write(sz)
+
+    def tetrahedra(self):
+        """vd_tetrahedra over the last build: the dual (regular / Delaunay)
+        tetrahedra whose power centre lies inside the box, int32 [T, 4], each
+        row ascending and rows grouped by their first site."""
+        import torch
+        dev = self.device
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        cnt = ctypes.c_int64(0)
+        with torch.cuda.device(dev):
+            _check(self.lib.vd_tetrahedra(self.handle, None, 0, ctypes.byref(cnt), ctypes.c_void_p(stream)),
+                   "vd_tetrahedra")
+            tets = torch.empty((cnt.value, 4), dtype=torch.int32, device=dev)
+            _check(self.lib.vd_tetrahedra(self.handle, _ptr(tets), cnt.value, ctypes.byref(cnt),
+                                          ctypes.c_void_p(stream)), "vd_tetrahedra")
+        return tets
 
     def backward(self, g_vol=None, g_cen=None, g_vert=None, want_w=True):
         """vd_backward over the last build: gradients of

@@ -39,6 +39,7 @@ struct vd_context {
     DevBuf st_vert[vd::kTiers], st_tri64[vd::kTiers], st_code[vd::kTiers], st_fsize[vd::kTiers], st_fv[vd::kTiers];
     DevBuf arena;  // per-worker cell arrays of the last (16384-vertex) pass
     DevBuf handoff;  // cells the 1024-vertex pass hands to the last one
+    DevBuf tet_cnt, tet_off;  // dual tetrahedra per cell and their offsets
     DevBuf bwd_facet, bwd_self, bwd_orphan;  // backward scratch
     // last build
     bool valid = false;
@@ -157,7 +158,8 @@ VD_API void vd_destroy(vd_context* c) {
                      &c->child, &c->pint, &c->pleaf, &c->range, &c->counters, &c->nodes, &c->hist, &c->stmp,
                      &c->bbox, &c->bpart, &c->misc, &c->loc, &c->cnt_v, &c->cnt_f, &c->cnt_n, &c->vol, &c->cen,
                      &c->flags, &c->offv, &c->offf, &c->offn, &c->scan_tmp, &c->stats,
-                     &c->ctr, &c->arena, &c->handoff, &c->bwd_facet, &c->bwd_self, &c->bwd_orphan};
+                     &c->ctr, &c->arena, &c->handoff, &c->tet_cnt, &c->tet_off, &c->bwd_facet, &c->bwd_self,
+                     &c->bwd_orphan};
     for (DevBuf* b : all) release(*b);
     if (c->ev_ready)
         for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -446,6 +448,36 @@ VD_API vd_status vd_write(vd_context* c, const vd_outputs* out, void* stream) {
         VD_HIP(hipEventRecord(c->ev[8], s));
         c->write_profiled = true;
     }
+    return VD_OK;
+}
+
+VD_API vd_status vd_tetrahedra(vd_context* c, int32_t* tets, int64_t capacity, int64_t* count, void* stream) {
+    g_err.clear();
+    if (!c || !count) return fail(VD_ERR_INVALID_ARG, "vd_tetrahedra: null argument");
+    if (!c->valid) return fail(VD_ERR_STATE, "vd_tetrahedra: no successful build");
+    VD_HIP(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = c->n;
+    VD_TRY(ensure(c->tet_cnt, (size_t)n * sizeof(uint32_t)));
+    VD_TRY(ensure(c->tet_off, (size_t)(n + 1) * sizeof(int64_t)));
+    vd::TetArgs a{};
+    a.n = n;
+    a.inv = as<uint32_t>(c->inv);
+    a.loc = as<uint32_t>(c->loc);
+    for (int t = 0; t < vd::kTiers; ++t) a.stage[t] = stage_of(c, t);
+    a.cnt_v = as<uint32_t>(c->cnt_v);
+    a.cnt_t = as<uint32_t>(c->tet_cnt);
+    a.off_t = as<int64_t>(c->tet_off);
+    VD_HIP(vd::launch_tet_count(a, s));
+    VD_HIP(vd::scan_counts(a.cnt_t, n, as<int64_t>(c->tet_off), as<int64_t>(c->scan_tmp), s));
+    int64_t total = 0;
+    VD_HIP(hipMemcpyAsync(&total, as<int64_t>(c->tet_off) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    VD_HIP(hipStreamSynchronize(s));
+    *count = total;
+    if (!tets) return VD_OK;
+    if (capacity < total) return fail(VD_ERR_INVALID_ARG, "vd_tetrahedra: capacity below the count");
+    a.tets = tets;
+    if (total > 0) VD_HIP(vd::launch_tet_write(a, s));
     return VD_OK;
 }
 

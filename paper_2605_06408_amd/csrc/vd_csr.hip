@@ -189,6 +189,75 @@ hipError_t launch_write(const WriteArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
+// ------------------------------------------------------------------ dual
+// The power diagram's dual is the regular triangulation of the weighted sites
+// (Sec. 3): each diagram vertex inside the box, where the cell of site i
+// meets three site facets j < k < l, is the centre of the tetrahedron
+// (i, j, k, l).  It is a vertex of those four cells; the cell of the smallest
+// of the four sites lists it.  One wave per cell, lanes over its vertices.
+__device__ __forceinline__ bool tet_row(const Stage& st, int64_t slot, int v, int64_t i, int32_t* c) {
+    const uint32_t tri = __float_as_uint(st.vert[slot * st.cap + v].w);
+    uint32_t r0 = tri & 1023u, r1 = (tri >> 10) & 1023u, r2 = (tri >> 20) & 1023u;
+    if (st.tri64) {
+        const uint64_t t = st.tri64[slot * st.cap + v];
+        r0 = (uint32_t)(t & 0x1FFFFFu);
+        r1 = (uint32_t)((t >> 21) & 0x1FFFFFu);
+        r2 = (uint32_t)((t >> 42) & 0x1FFFFFu);
+    }
+    const int32_t* C = st.code + slot * st.cap;
+    c[0] = C[r0];
+    c[1] = C[r1];
+    c[2] = C[r2];
+    return c[0] > i;  // codes ascend: the smallest is a site above i, so are all
+}
+
+template <bool kWrite>
+__global__ __launch_bounds__(256) void k_tets(TetArgs a) {
+    const int ln = threadIdx.x & 63;
+    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    for (int64_t i = wave; i < a.n; i += nwaves) {
+        const uint32_t loc = a.loc[a.inv[i]];
+        const uint32_t tier = loc >> 30;
+        const Stage st = tier == 0 ? a.stage[0] : (tier == 1 ? a.stage[1] : (tier == 2 ? a.stage[2] : a.stage[3]));
+        const int64_t slot = loc & 0x3FFFFFFFu;
+        const int nv = (int)a.cnt_v[i];
+        int64_t pos = kWrite ? a.off_t[i] : 0;
+        for (int v0 = 0; v0 < nv; v0 += 64) {
+            const int v = v0 + ln;
+            int32_t c[3] = {0, 0, 0};
+            const bool t = v < nv && tet_row(st, slot, v, i, c);
+            const uint64_t m = __ballot(t);
+            if (kWrite && t) {
+                int32_t* row = a.tets + 4 * (pos + (int64_t)__builtin_amdgcn_mbcnt_hi(
+                                                         (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u)));
+                row[0] = (int32_t)i;
+                row[1] = c[0];
+                row[2] = c[1];
+                row[3] = c[2];
+            }
+            pos += __popcll(m);
+        }
+        if (!kWrite && ln == 0) a.cnt_t[i] = (uint32_t)pos;
+    }
+}
+
+static int64_t tet_blocks(int64_t n) {
+    int64_t waves = n < 65536 ? n : 65536;
+    int64_t blocks = (waves * 64 + 255) / 256;
+    return blocks < 1 ? 1 : blocks;
+}
+
+hipError_t launch_tet_count(const TetArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_tets<false>, dim3((unsigned)tet_blocks(a.n)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_tet_write(const TetArgs& a, hipStream_t s) {
+    hipLaunchKernelGGL(k_tets<true>, dim3((unsigned)tet_blocks(a.n)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
 __global__ void k_set_i64(int64_t* dst, int64_t value) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *dst = value;
 }

@@ -221,6 +221,21 @@ size_t arena_bytes_per_worker();
 hipError_t launch_clip(const ClipArgs& a, int workers, void* arena, hipStream_t s);
 hipError_t launch_set_i64(int64_t* dst, int64_t value, hipStream_t s);
 hipError_t launch_write(const WriteArgs& a, hipStream_t s);
+
+// Dual tetrahedra of the staged cells (see vd_tetrahedra): count per cell,
+// then write rows at the scanned offsets.
+struct TetArgs {
+    int64_t n;
+    const uint32_t* inv;      // original index -> Morton position
+    const uint32_t* loc;
+    Stage stage[kTiers];
+    const uint32_t* cnt_v;
+    uint32_t* cnt_t;          // [n] tetrahedra per cell (count pass)
+    const int64_t* off_t;     // [n+1] their offsets (write pass)
+    int32_t* tets;            // [4 * total] out
+};
+hipError_t launch_tet_count(const TetArgs& a, hipStream_t s);
+hipError_t launch_tet_write(const TetArgs& a, hipStream_t s);
 hipError_t launch_backward(const BwdArgs& a, hipStream_t s);
 
 }  // namespace vd

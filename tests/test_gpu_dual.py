@@ -1,0 +1,125 @@
+"""Dual output (vd_tetrahedra) against the oracle's dual tetrahedra: rows are
+listed by the cell of their smallest site, so on every cell the oracle
+certifies the rows the library lists for it must equal the oracle's exactly.
+Whole diagrams at sizes the oracle finishes in seconds, and a sample of cells
+at the full 1M-site sizes."""
+import numpy as np
+import pytest
+
+from paper_2605_06408_amd import workloads as wl
+
+from .parity import gpu_build
+
+pytestmark = pytest.mark.gpu
+
+TAU32 = 1e-5
+
+
+def _gpu_tets(xyz, w, box, **kw):
+    import paper_2605_06408_amd as vd
+    import torch
+    import time
+    d = gpu_build(xyz, w, box, **kw)
+    t0 = time.perf_counter()
+    t = vd.context(torch.device("cuda", 0)).tetrahedra()
+    torch.cuda.synchronize()
+    print("vd_tetrahedra: %d sites, %d rows, %.2f ms (count, scan, write)"
+          % (len(xyz), len(t), 1e3 * (time.perf_counter() - t0)))
+    return d, t.cpu().numpy().astype(np.int64)
+
+
+def _structure(t, n):
+    """Rows ascending within, grouped by first site in ascending order, ids in range."""
+    if len(t) == 0:
+        return
+    assert np.all(t[:, :3] < t[:, 1:])
+    assert np.all(np.diff(t[:, 0]) >= 0)
+    assert t.min() >= 0 and t.max() < n
+
+
+def _by_first(t):
+    out = {}
+    for r in t.tolist():
+        out.setdefault(r[0], set()).add(tuple(r))
+    return out
+
+
+def _check(oracle_mod, t, o, min_certified_frac=0.9):
+    g = _by_first(t)
+    ot = _by_first(oracle_mod.tetrahedra(o))
+    cert = 0
+    fail = []
+    for k, i in enumerate(o["ids"].tolist()):
+        if o["margin"][k] < TAU32:
+            continue
+        cert += 1
+        if g.get(i, set()) != ot.get(i, set()):
+            fail.append((i, sorted(g.get(i, set()) ^ ot.get(i, set()))[:4]))
+    print("dual: %d rows, %d cells certified of %d, %d mismatching" % (len(t), cert, len(o["ids"]), len(fail)))
+    assert not fail, fail[:5]
+    assert cert >= min_certified_frac * len(o["ids"])
+
+
+@pytest.mark.parametrize("case", ["uniform_10k", "power_20k", "clustered_20k", "paper_clusters5_w_20k"])
+def test_whole_diagram(oracle_mod, case):
+    if case == "uniform_10k":
+        xyz, w, box = wl.make("uniform_10k", 0)
+    elif case == "power_20k":
+        xyz, w, box = wl.power_uniform(20000, 3)
+    elif case == "clustered_20k":
+        xyz, w, box = wl.clustered(20000, 3)
+    else:
+        xyz, w, box = wl.make("paper_clusters5_w_1m", 3, n=20000)
+    d, t = _gpu_tets(xyz, w, box)
+    _structure(t, len(xyz))
+    o = oracle_mod.cells(xyz, w, box)
+    _check(oracle_mod, t, o)
+    # one tetrahedron per diagram vertex off the box, each such vertex shared by four cells (cells
+    # built independently in FP32 may disagree only near a degeneracy)
+    vp = d.vert_planes.cpu().numpy()
+    shared = int(np.sum(vp[:, 0] >= 0))
+    print("vertices off the box %d, 4 x rows %d" % (shared, 4 * len(t)))
+    assert abs(shared - 4 * len(t)) <= 1e-3 * shared
+
+
+@pytest.mark.parametrize("n", [1, 3, 4, 5, 65, 4097])
+def test_ragged_and_tiny(oracle_mod, n):
+    xyz, w, box = wl.uniform(n, 7)
+    _, t = _gpu_tets(xyz, w, box)
+    _structure(t, n)
+    o = oracle_mod.cells(xyz, w, box)
+    _check(oracle_mod, t, o, min_certified_frac=0.0)
+    if n < 4:
+        assert len(t) == 0
+
+
+def test_count_only_and_capacity():
+    import ctypes
+    import paper_2605_06408_amd as vd
+    import torch
+    xyz, w, box = wl.uniform(5000, 2)
+    gpu_build(xyz, w, box)
+    ctx = vd.context(torch.device("cuda", 0))
+    cnt = ctypes.c_int64(-1)
+    stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+    assert ctx.lib.vd_tetrahedra(ctx.handle, None, 0, ctypes.byref(cnt), stream) == 0
+    assert cnt.value > 0
+    small = torch.full((cnt.value - 1, 4), -7, dtype=torch.int32, device="cuda")
+    st = ctx.lib.vd_tetrahedra(ctx.handle, ctypes.c_void_p(small.data_ptr()), cnt.value - 1, ctypes.byref(cnt), stream)
+    assert st != 0  # capacity below the count is rejected, nothing written
+    torch.cuda.synchronize()
+    assert bool((small == -7).all())
+    t1 = ctx.tetrahedra()
+    t2 = ctx.tetrahedra()
+    assert t1.shape == (cnt.value, 4) and torch.equal(t1, t2)
+
+
+@pytest.mark.parametrize("name", ["clustered_1m", "power_uniform_1m"])
+def test_one_million_sampled(oracle_mod, name):
+    xyz, w, box = wl.make(name, 0)
+    _, t = _gpu_tets(xyz, w, box)
+    _structure(t, len(xyz))
+    ids = np.sort(np.random.default_rng(4).choice(len(xyz), 300, replace=False))
+    o = oracle_mod.cells(xyz, w, box, ids=ids)
+    sel = np.isin(t[:, 0], ids)
+    _check(oracle_mod, t[sel], o)
