@@ -515,13 +515,13 @@ struct Cell {
                     const float a = v.a[k], b = v.b[k], c = v.c[k];
                     mn0 = fminf(mn0, a); mn1 = fminf(mn1, b); mn2 = fminf(mn2, c);
                     mx0 = fmaxf(mx0, a); mx1 = fmaxf(mx1, b); mx2 = fmaxf(mx2, c);
-                    r2 = fmaxf(r2, fmaf(a, a, fmaf(b, b, c * c)));
+                    if (A.culling == 2) r2 = fmaxf(r2, fmaf(a, a, fmaf(b, b, c * c)));
                 }
             }
         }
         float l0 = wmin(mn0), l1 = wmin(mn1), l2 = wmin(mn2);
         float h0 = wmax(mx0), h1 = wmax(mx1), h2 = wmax(mx2);
-        riso2 = wmax(r2);
+        riso2 = A.culling == 2 ? wmax(r2) : 0.f;  // the isotropic radius only serves culling mode 2
         if constexpr (G > 1) {
             const uint32_t v[7] = {__float_as_uint(l0), __float_as_uint(l1), __float_as_uint(l2), __float_as_uint(h0),
                                    __float_as_uint(h1), __float_as_uint(h2), __float_as_uint(riso2)};
@@ -1346,17 +1346,17 @@ struct Cell {
         float ax = 0.f, ay = 0.f, az = 0.f, a2 = 0.f, b = 0.f, dw = 0.f, key = INFINITY;
         float4 q = make_float4(0.f, 0.f, 0.f, 0.f);
         bool cand = false;
-        if (ln < nsite) {
-            uint32_t j = first + ln;
+        {
+            // every lane loads (lanes past the leaf repeat its last site) so
+            // that the arithmetic runs without a divergent branch
+            const uint32_t j = first + ((uint32_t)ln < nsite ? (uint32_t)ln : nsite - 1u);
             q = A.pts[j];
-            if (j != self && q.w != -INFINITY) {
-                ax = q.x - px; ay = q.y - py; az = q.z - pz;
-                a2 = fmaf(ax, ax, fmaf(ay, ay, az * az));
-                dw = pw - q.w;
-                b = 0.5f * (a2 + dw);
-                cand = a2 > 0.f;
-                key = b * __builtin_amdgcn_rsqf(a2);  // orders candidates only
-            }
+            ax = q.x - px; ay = q.y - py; az = q.z - pz;
+            a2 = fmaf(ax, ax, fmaf(ay, ay, az * az));
+            dw = pw - q.w;
+            b = 0.5f * (a2 + dw);
+            cand = (uint32_t)ln < nsite && j != self && q.w != -INFINITY && a2 > 0.f;
+            key = cand ? b * __builtin_amdgcn_rsqf(a2) : INFINITY;  // orders candidates only
         }
         auto keep = [&](bool c) -> bool {
             if (!c) return false;
@@ -1444,12 +1444,11 @@ struct Cell {
                 bool cull = true;
                 uint32_t ref = 0;
                 NodeChild cc;
-                if (ln < 2) {
-                    load_child(node, (int)ln, &cc);
-                    node_test(cc, &key, &cull, &delta);
-                    ref = cc.ref;
-                }
-                bool c0 = rdl((int)cull, 0) != 0, c1 = rdl((int)cull, 1) != 0;
+                load_child(node, (int)(ln & 1), &cc);
+                node_test(cc, &key, &cull, &delta);
+                ref = cc.ref;
+                const uint64_t cm = ballot(cull);
+                bool c0 = (cm & 1ull) != 0, c1 = (cm & 2ull) != 0;
                 if (A.culling == 3) {
                     if (!c0 && !c1) {
                         bool h0, h1;
@@ -1498,11 +1497,9 @@ struct Cell {
                 bool cull = true;
                 uint32_t ref = 0;
                 NodeChild c;
-                if (ln == 0) {
-                    load_child(e >> 1, (int)(e & 1), &c);
-                    node_test(c, &key, &cull, &delta);
-                    ref = c.ref;
-                }
+                load_child(e >> 1, (int)(e & 1), &c);
+                node_test(c, &key, &cull, &delta);
+                ref = c.ref;
                 bool culled = rdl((int)cull, 0) != 0;
                 if (!culled && A.culling == 3 && !ball_hit_lane(c, 0)) culled = true;
                 if (!culled) {
