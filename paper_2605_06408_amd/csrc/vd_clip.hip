@@ -1828,11 +1828,10 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
     // Cells are split into kWorkRanges contiguous (Morton-ordered) ranges, one
     // per XCD: the waves of workgroup b take chunks of their own range b % 8
     // first, so neighbouring cells (which walk the same nodes and sites) share
-    // one L2, then help the other ranges.  Chunks cut the atomics per cell in
-    // the first pass; the later passes take the few cells that overflowed one
-    // at a time, so that no worker builds several of them in a row while
-    // others idle.
-    const uint32_t chunk = ka->list ? 1u : (uint32_t)kWorkChunk;
+    // one L2, then help the other ranges.  A worker claims one cell at a time:
+    // in the later passes, which get the few cells that overflowed, claiming
+    // several made one worker build several large cells in a row while others
+    // idled, and in the first pass single claims also end the pass sooner.
     uint32_t r = blockIdx.x % kWorkRanges;
     int tried = 0;
     uint32_t cur = 0, end = 0;
@@ -1843,11 +1842,11 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
                 const uint32_t lo = (uint32_t)((uint64_t)count * r / kWorkRanges);
                 const uint32_t hi = (uint32_t)((uint64_t)count * (r + 1) / kWorkRanges);
                 uint32_t c0 = 0;
-                if (C.ln == 0 && C.lead()) c0 = atomicAdd(&cold_args()->work_counter[r], chunk);
+                if (C.ln == 0 && C.lead()) c0 = atomicAdd(&cold_args()->work_counter[r], 1u);
                 c0 = C.bcast(c0);
                 if (c0 < hi - lo) {
                     cur = lo + c0;
-                    end = min(hi, cur + chunk);
+                    end = cur + 1;
                     got = true;
                     break;
                 }

@@ -13,9 +13,8 @@ constexpr int kMaxLeaf = 64;                 // leaf refs store count-1 in 6 bit
 constexpr int64_t kMaxSites = int64_t(1) << 25;  // leaf refs store `first` in 25 bits
 constexpr int kDefaultLeaf = 32;
 // Work distribution of the clip kernels: one contiguous range of cells per
-// XCD (workgroup b runs on XCD b % 8), taken kWorkChunk cells at a time.
+// XCD (workgroup b runs on XCD b % 8), claimed one cell at a time.
 constexpr int kWorkRanges = 8;
-constexpr int kWorkChunk = 4;
 // Vertex (= plane) capacity of a cell in each clipping pass.
 constexpr int kTiers = 4;
 constexpr int kTierCap[kTiers] = {64, 256, 1024, 16384};
