@@ -47,9 +47,9 @@ PEAK_HBM_GBS = 8000.0
 # device copy in the same run (FETCH_SIZE 131088.4 KiB -> x2.0, WRITE_SIZE
 # 262144.0 KiB -> x1.0).  Valid only while the kernel source is unchanged.
 TRAFFIC_MEASURED = {
-    "sources_sha1": {"paper_2605_06408_amd/csrc/vd_clip.hip": "6f157c94ab24ae9abae3fcd9a57d906b196ed8c6",
-                     "paper_2605_06408_amd/csrc/vd_internal.h": "f7eda386bb470bacbcca6a750bedaa099a763b2a"},
-    "workload": "clustered_1m", "fetch_kib": 105606.4, "write_kib": 1315648.4, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sources_sha1": {"paper_2605_06408_amd/csrc/vd_clip.hip": "b002ce06ce6aedbf6e1e279cbc3d4818812120b1",
+                     "paper_2605_06408_amd/csrc/vd_internal.h": "661a515ca8e5fede4dd2562752156d51cabc0bc5"},
+    "workload": "clustered_1m", "fetch_kib": 28098.6, "write_kib": 896496.9, "fetch_scale": 2.0, "write_scale": 1.0,
 }
 
 
