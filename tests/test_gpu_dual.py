@@ -123,3 +123,28 @@ def test_one_million_sampled(oracle_mod, name):
     o = oracle_mod.cells(xyz, w, box, ids=ids)
     sel = np.isin(t[:, 0], ids)
     _check(oracle_mod, t[sel], o)
+
+
+def test_rows_match_vertex_planes_of_very_large_cells(oracle_mod):
+    """Cells of up to thousands of vertices (the 1024- and 16384-vertex passes,
+    whose staged records pack facet ranks differently) list exactly the rows
+    that their vertices in vd_write name; the sampled certified cells match
+    the oracle."""
+    from .test_gpu_parity import _heavy_sites
+    xyz, w, box, big = _heavy_sites(40000, 21)
+    d, t = _gpu_tets(xyz, w, box)
+    assert d.sizes["n_huge"] >= 1
+    _structure(t, len(xyz))
+    vo = d.vert_off.cpu().numpy()
+    vp = d.vert_planes.cpu().numpy().astype(np.int64)
+    owner = np.repeat(np.arange(len(xyz)), np.diff(vo))
+    sel = vp[:, 0] > owner
+    want = np.column_stack([owner[sel], vp[sel]])
+    assert np.array_equal(t, want)  # same rows in the same order
+    for i in range(big):
+        nv = int(vo[i + 1] - vo[i])
+        print("cell %d: %d vertices, %d rows" % (i, nv, int(np.sum(t[:, 0] == i))))
+    assert int(vo[1] - vo[0]) > 1024
+    ids = np.sort(np.random.default_rng(6).choice(len(xyz), 400, replace=False))
+    o = oracle_mod.cells(xyz, w, box, ids=ids)
+    _check(oracle_mod, t[np.isin(t[:, 0], ids)], o, min_certified_frac=0.8)
