@@ -92,3 +92,31 @@ def test_each_tet_is_a_vertex_of_its_four_cells(oracle_mod):
 def test_no_tets_without_four_sites(oracle_mod):
     xyz = np.array([[0.2, 0.3, 0.4], [0.7, 0.6, 0.5], [0.4, 0.8, 0.1]], np.float32)
     assert oracle_mod.tetrahedra(oracle_mod.cells(xyz, None, UNIT)).shape == (0, 4)
+
+
+def test_weighted_match_qhull_lifted_lower_hull(oracle_mod):
+    """The regular triangulation is the projection of the lower convex hull of
+    the lifted points (p, |p|^2 - w) (Aurenhammer's lifting map): its facets
+    whose power centre lies in the box are the oracle's tetrahedra."""
+    from scipy.spatial import ConvexHull
+    xyz, w, box = wl.power_uniform(1500, 9)
+    w = (w * 0.3).astype(np.float32)
+    box = np.asarray(box, np.float64)
+    got = {tuple(r) for r in oracle_mod.tetrahedra(oracle_mod.cells(xyz, w, box)).tolist()}
+    p = xyz.astype(np.float64)
+    wd = w.astype(np.float64)
+    hull = ConvexHull(np.hstack([p, (p * p).sum(1, keepdims=True) - wd[:, None]]))
+    want, near = set(), set()
+    for s, eq in zip(hull.simplices, hull.equations):
+        if eq[3] >= 0:
+            continue  # upper hull
+        a = 2.0 * (p[s[1:]] - p[s[0]])
+        rhs = (p[s[1:]] ** 2).sum(1) - wd[s[1:]] - (p[s[0]] ** 2).sum() + wd[s[0]]
+        z = np.linalg.solve(a, rhs)  # power centre
+        key = tuple(sorted(int(x) for x in s))
+        if _inside(z, box, 1e-9):
+            want.add(key)
+        elif _inside(z, box, -1e-9):
+            near.add(key)
+    assert len(want) > 500
+    assert want <= got and got - want <= near
