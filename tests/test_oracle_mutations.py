@@ -6,7 +6,9 @@ writing the method from the paper: a weight sign in the radical plane
 (Sec. 4.2, Eq. 2), a dropped factor, a transposed operand in the vertex
 solve, a box face on the wrong side, a wrong tetrahedron centroid weight, a
 clockwise facet, a premature stop of the candidate walk, a squared radius,
-a fan without its reference point, the wrong winner among coincident sites.
+a fan without its reference point, the wrong winner among coincident sites;
+and, for the dual tetrahedra read off the cells, box vertices kept, every
+cell listing the tetrahedron, the vertices of the wrong cell.
 """
 import os
 import shutil
@@ -84,6 +86,35 @@ def test_planted_gradient_mistake_is_caught(name, tmp_path):
     code = ("import sys; sys.path.insert(0, %r); sys.path.insert(1, %r); import pytest; "
             "sys.exit(pytest.main(['-q', '-x', '-p', 'no:cacheprovider', '--import-mode=append', %r]))"
             % (str(tmp_path), ROOT, os.path.join(ROOT, "tests", "test_oracle_grad.py")))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=str(tmp_path),
+                       timeout=600)
+    assert r.returncode == 1, "mutant %s survived the pins:\n%s" % (name, r.stdout[-2000:])
+
+
+# Mistakes in reading the dual tetrahedra off the cells.
+DUAL_MUTANTS = {
+    "box_vertices_kept": ("            if c[0] > i:\n", "            if c[2] > i:\n"),
+    "listed_by_every_cell": ("            if c[0] > i:\n", "            if c[0] >= 0:\n"),
+    "neighbouring_cell": ('codes = res["vert_code"][res["vert_off"][t]:res["vert_off"][t + 1]]',
+                          'codes = res["vert_code"][res["vert_off"][t]:res["vert_off"][min(t + 2, len(res["ids"]))]]'),
+}
+
+
+@pytest.mark.parametrize("name", sorted(DUAL_MUTANTS))
+def test_planted_dual_mistake_is_caught(name, tmp_path):
+    src = open(os.path.join(ROOT, "oracle", "__init__.py")).read()
+    old, new = DUAL_MUTANTS[name]
+    assert src.count(old) == 1, "mutation site moved"
+    pkg = tmp_path / "oracle"
+    pkg.mkdir()
+    for f in ("brute.py", "grad.py", "vd_oracle.cpp"):
+        shutil.copy(os.path.join(ROOT, "oracle", f), pkg / f)
+    (pkg / "__init__.py").write_text(src.replace(old, new))
+    subprocess.run(["g++", "-O1", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o",
+                    str(pkg / "liboracle.so"), str(pkg / "vd_oracle.cpp")], check=True)
+    code = ("import sys; sys.path.insert(0, %r); sys.path.insert(1, %r); import pytest; "
+            "sys.exit(pytest.main(['-q', '-x', '-p', 'no:cacheprovider', '--import-mode=append', %r]))"
+            % (str(tmp_path), ROOT, os.path.join(ROOT, "tests", "test_oracle_dual.py")))
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=str(tmp_path),
                        timeout=600)
     assert r.returncode == 1, "mutant %s survived the pins:\n%s" % (name, r.stdout[-2000:])
