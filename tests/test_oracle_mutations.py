@@ -7,8 +7,11 @@ writing the method from the paper: a weight sign in the radical plane
 solve, a box face on the wrong side, a wrong tetrahedron centroid weight, a
 clockwise facet, a premature stop of the candidate walk, a squared radius,
 a fan without its reference point, the wrong winner among coincident sites;
-and, for the dual tetrahedra read off the cells, box vertices kept, every
-cell listing the tetrahedron, the vertices of the wrong cell.
+for the dual tetrahedra read off the cells, box vertices kept, every cell
+listing the tetrahedron, the vertices of the wrong cell; and for the
+robustness margin that decides which cells the bit-exact gate covers, a
+constant margin, box faces left out, the vertex error scale left out, and the
+weight shift of the empty-cell certificate with the wrong sign.
 """
 import os
 import shutil
@@ -118,3 +121,33 @@ def test_planted_dual_mistake_is_caught(name, tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=str(tmp_path),
                        timeout=600)
     assert r.returncode == 1, "mutant %s survived the pins:\n%s" % (name, r.stdout[-2000:])
+
+
+# Mistakes in the robustness margin (which cells the bit-exact gate covers)
+# and in the certificate of empty power cells.
+MARGIN_MUTANTS = {
+    "constant_margin": ("return std::max(margin, 0.0);", "return tau_m;"),
+    "margin_without_box_faces": ("for (const Plane& h : boxp.pl) visit(h);", ""),
+    "margin_without_vertex_error": ("double sigma = ev[k] + norm3(v.y) + dk;", "double sigma = norm3(v.y) + dk;"),
+    "empty_certificate_shift_sign": ("h.b += 0.5 * wshift;", "h.b -= 0.5 * wshift;"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(MARGIN_MUTANTS))
+def test_planted_margin_mistake_is_caught(name, tmp_path):
+    src = open(os.path.join(ROOT, "oracle", "vd_oracle.cpp")).read()
+    old, new = MARGIN_MUTANTS[name]
+    assert src.count(old) == 1, "mutation site moved"
+    pkg = tmp_path / "oracle"
+    pkg.mkdir()
+    for f in ("__init__.py", "brute.py", "grad.py"):
+        shutil.copy(os.path.join(ROOT, "oracle", f), pkg / f)
+    (pkg / "vd_oracle.cpp").write_text(src.replace(old, new))
+    subprocess.run(["g++", "-O1", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o",
+                    str(pkg / "liboracle.so"), str(pkg / "vd_oracle.cpp")], check=True)
+    code = ("import sys; sys.path.insert(0, %r); sys.path.insert(1, %r); import pytest; "
+            "sys.exit(pytest.main(['-q', '-p', 'no:cacheprovider', '--import-mode=append', %r]))"
+            % (str(tmp_path), ROOT, os.path.join(ROOT, "tests", "test_oracle_margin.py")))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=str(tmp_path),
+                       timeout=600)
+    assert r.returncode == 1, "mutant %s survived the margin pins:\n%s" % (name, r.stdout[-2000:])
