@@ -191,6 +191,11 @@ VD_API vd_status vd_write(vd_context* ctx, const vd_outputs* out, void* stream);
  *   g_w     device float[n] out, or NULL to skip (computed also for Voronoi
  *           builds, as the derivative at w = 0)
  * An empty cell has V = 0 and c = p_i, so it passes g_cen[i] to its site.
+ * A box given to vd_build is held fixed.  Without one the box is the sites'
+ * bounding box, whose faces move with the extreme sites: the sum over all
+ * cells of dL/db of each face then goes to the lowest-index site on that
+ * face (b = p_i,k - min_j p_j,k for a lower face, max_j p_j,k - p_i,k for an
+ * upper one).
  * Stream-ordered, does not synchronise; the output is deterministic except
  * where a facet is not listed back by its neighbour (FP32-undecidable
  * configurations), whose share is added atomically.  VD_ERR_STATE without a

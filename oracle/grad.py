@@ -24,6 +24,12 @@ for a site plane and db_f = -a_f . dp_i for a box face.
 
 For an empty cell V = 0 and c = p_i.
 
+When no clip box is given, the box is the bounding box of the sites, so its
+faces move with the extreme sites: b_f = p_i,k - min_j p_j,k for a lower face
+and max_j p_j,k - p_i,k for an upper one.  The sum over all cells of dL/db_f
+for each face then goes, with sign -1 (lower) or +1 (upper), to the site
+that attains that minimum or maximum (the lowest index among ties).
+
 The closed forms that follow for the volume (dV_i/dw_j = -A_ij / (2 D_ij),
 dV_i/dp_j = -(A_ij / D_ij)(X_ij - p_j) with X_ij the facet centroid) are
 checked in the tests; the whole chain is pinned by FP64 central finite
@@ -72,12 +78,14 @@ def _facet_integrals(poly, a):
     return A, AY, S
 
 
-def cell_partials(xyz, w, box, res, t, g_vol=0.0, g_cen=None, g_vert_fn=None):
+def cell_partials(xyz, w, box, res, t, g_vol=0.0, g_cen=None, g_vert_fn=None, box_db=None):
     """Contributions of cell t of an oracle result to dL/dp and dL/dw, for
     L = g_vol V_i + g_cen . c_i + sum_v phi(x_v) with grad phi = g_vert_fn.
     g_vert_fn(x [k,3], codes [k,3], i) gives the gradient on the cell's
     vertices (positions, ascending plane codes, site).
-    Returns {site: (dL/dp (3,), dL/dw)}."""
+    Returns {site: (dL/dp (3,), dL/dw)}, the box faces held fixed; with
+    ``box_db`` (an array of 6) dL/db_f of the cell's box faces is added to
+    box_db[-code - 1]."""
     i = int(res["ids"][t])
     cv = cell_view(res, t)
     gc = np.zeros(3) if g_cen is None else np.asarray(g_cen, float)
@@ -131,13 +139,16 @@ def cell_partials(xyz, w, box, res, t, g_vol=0.0, g_cen=None, g_vert_fn=None):
             add(i, -gp, 0.5 * dB[c])
         else:
             add(i, -dB[c] * a, 0.0)
+            if box_db is not None:
+                box_db[-c - 1] += dB[c]
     return {k: (v[0], v[1]) for k, v in out.items()}
 
 
 def backward(xyz, w, box, g_vol=None, g_cen=None, g_vert_fn=None, ids=None, fp64=False):
     """dL/dp [n,3] and dL/dw [n] for L = sum_i g_vol_i V_i + g_cen_i . c_i
     + sum over all vertices phi(x) (grad phi = g_vert_fn(x, codes, i), see
-    ``cell_partials``).
+    ``cell_partials``).  ``box`` None: the box is the sites' bounding box and
+    its faces carry gradient to the extreme sites (all cells are needed).
 
     With ``ids`` the gradients are exact only at those sites: the cells of
     the sites and of all their neighbours are computed (a site's gradient
@@ -146,8 +157,14 @@ def backward(xyz, w, box, g_vol=None, g_cen=None, g_vert_fn=None, ids=None, fp64
     dt = np.float64 if fp64 else np.float32
     x64 = np.asarray(xyz, dt).astype(np.float64)
     w64 = None if w is None else np.asarray(w, dt).astype(np.float64)
+    moving_box = box is None
+    if moving_box:
+        if ids is not None:
+            raise ValueError("a box that follows the sites needs every cell (ids=None)")
+        box = np.concatenate([x64.min(axis=0), x64.max(axis=0)])
     box64 = np.asarray(box, dt).astype(np.float64)
     n = len(x64)
+    box_db = np.zeros(6) if moving_box else None
     if ids is None:
         need = np.arange(n)
     else:
@@ -160,10 +177,16 @@ def backward(xyz, w, box, g_vol=None, g_cen=None, g_vert_fn=None, ids=None, fp64
         i = int(need[t])
         part = cell_partials(x64, w64, box64, res, t,
                              0.0 if g_vol is None else float(g_vol[i]),
-                             None if g_cen is None else g_cen[i], g_vert_fn)
+                             None if g_cen is None else g_cen[i], g_vert_fn, box_db)
         for s, (a, b) in part.items():
             gp[s] += a
             gw[s] += b
+    if moving_box:
+        for c in range(6):
+            ax, side = c >> 1, c & 1
+            col = x64[:, ax]
+            j = int(np.argmax(col)) if side else int(np.argmin(col))  # first index among ties
+            gp[j, ax] += box_db[c] if side else -box_db[c]
     return gp, gw, res
 
 

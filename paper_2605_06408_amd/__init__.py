@@ -266,7 +266,7 @@ class Context:
 
         gv = arg(g_vol, (n,))
         gc = arg(g_cen, (n, 3))
-        gx = None if g_vert is None else arg(g_vert, (g_vert.shape[0], 3))
+        gx = None if g_vert is None else arg(g_vert, (self.last_sizes["n_vert"], 3))
         g_xyz = torch.empty((n, 3), dtype=torch.float32, device=dev)
         g_w = torch.empty(n, dtype=torch.float32, device=dev) if want_w else None
         stream = torch.cuda.current_stream(dev).cuda_stream

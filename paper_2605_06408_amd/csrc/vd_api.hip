@@ -40,7 +40,7 @@ struct vd_context {
     DevBuf arena;  // per-worker cell arrays of the last (16384-vertex) pass
     DevBuf handoff;  // cells the 1024-vertex pass hands to the last one
     DevBuf tet_cnt, tet_off;  // dual tetrahedra per cell and their offsets
-    DevBuf bwd_facet, bwd_self, bwd_orphan;  // backward scratch
+    DevBuf bwd_facet, bwd_self, bwd_orphan, bwd_box;  // backward scratch
     // last build
     bool valid = false;
     int64_t n = 0;
@@ -53,6 +53,7 @@ struct vd_context {
     bool ev_ready = false;
     bool profiled = false, write_profiled = false, bwd_profiled = false;
     bool counted = false;
+    bool box_given = false;  // false: the box of the last build is the sites' bounding box
 };
 
 namespace {
@@ -159,7 +160,7 @@ VD_API void vd_destroy(vd_context* c) {
                      &c->bbox, &c->bpart, &c->misc, &c->loc, &c->cnt_v, &c->cnt_f, &c->cnt_n, &c->vol, &c->cen,
                      &c->flags, &c->offv, &c->offf, &c->offn, &c->scan_tmp, &c->stats,
                      &c->ctr, &c->arena, &c->handoff, &c->tet_cnt, &c->tet_off, &c->bwd_facet, &c->bwd_self,
-                     &c->bwd_orphan};
+                     &c->bwd_orphan, &c->bwd_box};
     for (DevBuf* b : all) release(*b);
     if (c->ev_ready)
         for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -307,6 +308,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     a.flags = as<uint8_t>(c->flags);
     a.stats = as<unsigned long long>(c->stats);
     a.ctr = o.counters ? as<unsigned long long>(c->ctr) : nullptr;
+    a.err = misc;
 
     // tier 0: every cell
     a.tier = 0;
@@ -399,6 +401,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     c->sizes = z;
     c->n = n;
     c->order = order;
+    c->box_given = bbox != nullptr;
     c->valid = true;
     *sizes = z;
     if (z.n_failed > 0)
@@ -517,9 +520,17 @@ VD_API vd_status vd_backward(vd_context* c, const float* g_vol, const float* g_c
     VD_TRY(ensure(c->bwd_facet, nf * sizeof(double4)));
     VD_TRY(ensure(c->bwd_self, (size_t)n * sizeof(double4)));
     VD_TRY(ensure(c->bwd_orphan, (size_t)n * 4 * sizeof(double)));
+    const int64_t nwaves = vd::bwd_waves(n);
+    const bool moving_box = !c->box_given;
+    // per-wave box-face partials, their 6 sums, then the 6 face sites
+    const size_t box_bytes = (size_t)(nwaves * 6 + 6) * sizeof(double) + 6 * sizeof(uint32_t);
+    if (moving_box) VD_TRY(ensure(c->bwd_box, box_bytes));
     const bool prof = c->profiled;
     if (prof) VD_HIP(hipEventRecord(c->ev[9], s));
     VD_HIP(hipMemsetAsync(c->bwd_orphan.p, 0, (size_t)n * 4 * sizeof(double), s));
+    double* box_part = moving_box ? as<double>(c->bwd_box) : nullptr;
+    uint32_t* box_arg = moving_box ? reinterpret_cast<uint32_t*>(box_part + nwaves * 6 + 6) : nullptr;
+    if (moving_box) VD_HIP(hipMemsetAsync(box_arg, 0xFF, 6 * sizeof(uint32_t), s));
     vd::BwdArgs a{};
     a.n = n;
     a.pts = as<float4>(c->spts);
@@ -540,6 +551,11 @@ VD_API vd_status vd_backward(vd_context* c, const float* g_vol, const float* g_c
     a.orphan = as<double>(c->bwd_orphan);
     a.g_xyz = g_xyz;
     a.g_w = g_w;
+    a.moving_box = moving_box ? 1 : 0;
+    a.pts_orig = as<float4>(c->pts);
+    a.box_part = box_part;
+    a.box_sum = moving_box ? box_part + nwaves * 6 : nullptr;
+    a.box_arg = box_arg;
     VD_HIP(vd::launch_backward(a, s));
     if (prof) {
         VD_HIP(hipEventRecord(c->ev[10], s));

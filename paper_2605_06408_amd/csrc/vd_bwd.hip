@@ -29,6 +29,10 @@
 // the site gradient they cancel to.
 // A facet whose neighbour does not list the cell back (possible only on
 // configurations FP32 cannot decide) is added with an atomic instead.
+// When the box is the sites' own bounding box its faces move with the
+// extreme sites (b = p_i,k - min_j p_j,k for a lower face, max_j p_j,k - p_i,k
+// for an upper one): the sum over all cells of dL/db of each face goes to the
+// site on that face with the lowest index, summed in a fixed order.
 #include "vd_internal.h"
 
 namespace vd {
@@ -144,6 +148,7 @@ __global__ __launch_bounds__(256) void k_bwd_cells(BwdArgs a) {
     const int ln = threadIdx.x & 63;
     const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
+    double bx[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // dL/db of the box faces of this lane's facets
     for (int64_t i = wave; i < a.n; i += nwaves) {
         const uint32_t k = a.inv[i];
         const float4 ps = a.pts[k];
@@ -303,6 +308,10 @@ __global__ __launch_bounds__(256) void k_bwd_cells(BwdArgs a) {
                     } else {
                         // box face: b = +-(B_k - p_i,k), a fixed
                         for (int q = 0; q < 3; ++q) self_p[q] -= dB * n[q];
+                        const int face = -code - 1;
+#pragma unroll
+                        for (int c = 0; c < 6; ++c)
+                            if (c == face) bx[c] += dB;
                     }
                 }
                 carry += (uint32_t)__shfl(x, 63);
@@ -312,6 +321,40 @@ __global__ __launch_bounds__(256) void k_bwd_cells(BwdArgs a) {
         self_w = wsum(self_w);
         if (ln == 0) a.gself[i] = make_double4(self_p[0] + gc[0], self_p[1] + gc[1], self_p[2] + gc[2], self_w);
     }
+    if (a.moving_box) {
+        for (int c = 0; c < 6; ++c) {
+            const double t = wsum(bx[c]);
+            if (ln == 0) a.box_part[wave * 6 + c] = t;
+        }
+    }
+}
+
+// Lowest original index of a site on each face of the sites' bounding box
+// (the box is their FP32 minimum and maximum, so some site equals each face).
+__global__ __launch_bounds__(256) void k_bwd_box_arg(BwdArgs a) {
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= a.n) return;
+    const float4 p = a.pts_orig[j];
+    const float v[3] = {p.x, p.y, p.z};
+#pragma unroll
+    for (int c = 0; c < 6; ++c)
+        if (v[c >> 1] == a.bbox[(c & 1) ? 3 + (c >> 1) : (c >> 1)]) atomicMin(&a.box_arg[c], (uint32_t)j);
+}
+
+// Sum of the per-wave box-face partials, in a fixed order (one block).
+__global__ __launch_bounds__(256) void k_bwd_box_sum(BwdArgs a, int64_t nwaves) {
+    __shared__ double red[6][256];
+    double s[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int64_t w = threadIdx.x; w < nwaves; w += 256)
+        for (int c = 0; c < 6; ++c) s[c] += a.box_part[w * 6 + c];
+    for (int c = 0; c < 6; ++c) red[c][threadIdx.x] = s[c];
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int c = 0; c < 6; ++c) red[c][threadIdx.x] += red[c][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x < 6) a.box_sum[threadIdx.x] = red[threadIdx.x][0];
 }
 
 // Per site: its own cell's share, then what each neighbour's cell sent it
@@ -338,6 +381,9 @@ __global__ __launch_bounds__(256) void k_bwd_gather(BwdArgs a) {
     }
     const double* o = a.orphan + 4 * j;
     for (int q = 0; q < 4; ++q) g[q] += o[q];
+    if (a.moving_box)
+        for (int c = 0; c < 6; ++c)
+            if (a.box_arg[c] == (uint32_t)j) g[c >> 1] += (c & 1) ? a.box_sum[c] : -a.box_sum[c];
     a.g_xyz[3 * j] = (float)g[0];
     a.g_xyz[3 * j + 1] = (float)g[1];
     a.g_xyz[3 * j + 2] = (float)g[2];
@@ -346,11 +392,20 @@ __global__ __launch_bounds__(256) void k_bwd_gather(BwdArgs a) {
 
 }  // namespace
 
+int64_t bwd_waves(int64_t n) {
+    const int64_t waves = n < 65536 ? n : 65536;
+    return (waves + 3) / 4 * 4;  // whole blocks of four waves
+}
+
 hipError_t launch_backward(const BwdArgs& a, hipStream_t s) {
     if (a.n < 1) return hipSuccess;
-    const int64_t waves = a.n < 65536 ? a.n : 65536;
-    const int64_t blocks = (waves * 64 + 255) / 256;
+    const int64_t waves = bwd_waves(a.n);
+    const int64_t blocks = waves / 4;
     hipLaunchKernelGGL(k_bwd_cells, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    if (a.moving_box) {
+        hipLaunchKernelGGL(k_bwd_box_arg, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(k_bwd_box_sum, dim3(1), dim3(256), 0, s, a, waves);
+    }
     hipLaunchKernelGGL(k_bwd_gather, dim3((unsigned)((a.n + 255) / 256)), dim3(256), 0, s, a);
     return hipGetLastError();
 }

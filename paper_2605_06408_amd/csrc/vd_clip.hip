@@ -1821,8 +1821,11 @@ struct Cell {
 // its exchange tables).
 template <int VPL, bool kLds, bool kCount, int G = 1>
 __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
-    Cell<VPL, kLds, kCount, G> C(M, A, gx);
     KArgs* ka = cold_args();
+    // the input checks (non-finite values, a flat box) ran before this pass:
+    // on such input no cell is built
+    if (*ka->err != 0u) return;
+    Cell<VPL, kLds, kCount, G> C(M, A, gx);
     const uint32_t count = ka->list ? *ka->list_count : (uint32_t)A.n;
     unsigned long long st_empty = 0, st_large = 0, st_unc = 0, st_fail = 0, st_fp64 = 0, st_res = 0;
     // Cells are split into kWorkRanges contiguous (Morton-ordered) ranges, one

@@ -133,6 +133,7 @@ struct ClipArgs {
     uint8_t* flags;           // [n]
     unsigned long long* stats;  // [kStatCount]
     unsigned long long* ctr;    // [kCtrCount] work counters, or null
+    const uint32_t* err;      // input error bits of this build (non-zero: do nothing)
 };
 
 struct WriteArgs {
@@ -177,7 +178,21 @@ struct BwdArgs {
     double* orphan;           // [4n], zeroed: shares of facets not listed back
     float* g_xyz;             // [3n] out
     float* g_w;               // [n] out, or null
+    // Box of the sites (the build was given no box): its faces move with the
+    // extreme sites.  Each wave of the cell pass sums dL/db of the box faces
+    // of its cells into box_part[wave * 6 + face]; box_sum[face] is their
+    // total and box_arg[face] (preset to 0xFFFFFFFF) the lowest original
+    // index of a site on that face.  moving_box = 0: faces held fixed.
+    int moving_box;
+    const float4* pts_orig;   // [n] sites in the caller's order
+    double* box_part;         // [bwd_waves(n) * 6]
+    double* box_sum;          // [6]
+    uint32_t* box_arg;        // [6]
 };
+
+// Waves of the backward cell pass (the size of BwdArgs.box_part is six
+// doubles per wave).
+int64_t bwd_waves(int64_t n);
 
 // ---------------------------------------------------------------- launches
 // (host wrappers; each returns the hipError_t of its launch)

@@ -9,7 +9,8 @@ Gate (readings of "bit-exact neighbours on inputs in general position" and
 "1e-5 relative geometry"): a cell whose oracle margin is at least `tau` is
 certified -- its combinatorics are far from any degeneracy at the precision
 compared -- and must match exactly: empty flag, neighbour list, vertex keys
-and facet polygons.  On certified non-empty cells, vertices and centroids must
+and facet polygons.  The plain FP32 form is gated at tau = 1e-5, the mixed
+FP32/FP64 form (FP64 re-evaluation of doubtful signs) at TAU_MIXED = 1e-10.  On certified non-empty cells, vertices and centroids must
 satisfy |x - x*|_inf / max(|x*|_inf, l) <= tol with l the diagonal of the
 cell's bounding box, and volumes |V - V*| / V* <= tol.  Uncertified cells are
 only counted.
@@ -17,6 +18,9 @@ only counted.
 from __future__ import annotations
 
 import numpy as np
+
+TAU_FP32 = 1e-5
+TAU_MIXED = 1e-10
 
 FIELDS = ("nbr_off", "nbr", "facet_off", "facet_nbr", "fv_off", "fv", "vert_off", "vert", "vert_planes", "vol",
           "centroid", "flags")
@@ -127,7 +131,10 @@ def compare(g: dict, o: dict, tau: float = 1e-5, tol: float = 1e-5, max_report: 
     """Compare GPU rows `g` and oracle rows `o` for the same cells (same order)."""
     assert np.array_equal(g["ids"], o["ids"])
     rep = dict(cells=len(g["ids"]), certified=0, topo_fail=[], geo_fail=[], uncertified=0,
-               uncertified_mismatch=0, max_vert_err=0.0, max_vol_err=0.0, max_cen_err=0.0, empty=0)
+               uncertified_mismatch=0, max_vert_err=0.0, max_vol_err=0.0, max_cen_err=0.0, empty=0, tau=tau)
+    # per certified non-empty cell: vertex (global, relative to max(|x*|, l)),
+    # vertex in the cell's frame (relative to l), volume and centroid errors
+    errs = {"vert": [], "vert_local": [], "vol": [], "cen": []}
     for t in range(len(g["ids"])):
         cert = o["margin"][t] >= tau
         ge = bool(g["flags"][t] & 1)
@@ -158,6 +165,10 @@ def compare(g: dict, o: dict, tau: float = 1e-5, tol: float = 1e-5, max_report: 
         vv = abs(float(g["vol"][t]) - float(o["vol"][t])) / float(o["vol"][t])
         c_ref = o["centroid"][t]
         ce = float(np.max(np.abs(g["centroid"][t].astype(np.float64) - c_ref))) / max(float(np.max(np.abs(c_ref))), ell)
+        errs["vert"].append(ve)
+        errs["vert_local"].append(max(float(np.max(np.abs(gv[k] - ov[k]))) for k in ov) / ell)
+        errs["vol"].append(vv)
+        errs["cen"].append(ce)
         rep["max_vert_err"] = max(rep["max_vert_err"], ve)
         rep["max_vol_err"] = max(rep["max_vol_err"], vv)
         rep["max_cen_err"] = max(rep["max_cen_err"], ce)
@@ -167,11 +178,20 @@ def compare(g: dict, o: dict, tau: float = 1e-5, tol: float = 1e-5, max_report: 
                                             gpu_vol=float(g["vol"][t]), oracle_vol=float(o["vol"][t]),
                                             gpu_vol_from_own_vertices=_poly_volume(gv, gf),
                                             gpu_flags=int(g["flags"][t]), nv=len(gv)))
+    rep["errs"] = {k: np.asarray(v, np.float64) for k, v in errs.items()}
     return rep
 
 
+def error_table(rep: dict) -> dict:
+    """p50 / p99 / max of each geometry error of a compare() report."""
+    out = {}
+    for k, v in rep["errs"].items():
+        out[k] = [float(np.quantile(v, 0.5)), float(np.quantile(v, 0.99)), float(v.max())] if len(v) else None
+    return out
+
+
 def assert_parity(rep: dict, min_certified_frac: float = 0.9):
-    msg = "parity report: %r" % {k: v for k, v in rep.items()}
+    msg = "parity report: %r" % {k: v for k, v in rep.items() if k != "errs"}
     print(msg)
     assert not rep["topo_fail"], msg
     assert not rep["geo_fail"], msg

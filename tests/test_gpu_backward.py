@@ -95,7 +95,7 @@ def _run_backward(xyz, w, box, g_vol, g_cen, with_vert):
     ctx = vd.Context(0)
     x = torch.from_numpy(xyz).cuda()
     ww = None if w is None else torch.from_numpy(w).cuda()
-    d = ctx.build(x, ww, bbox=[float(v) for v in box])
+    d = ctx.build(x, ww, bbox=None if box is None else [float(v) for v in box])
     gv = torch.from_numpy(g_vol.astype(np.float32)).cuda()
     gc = torch.from_numpy(g_cen.astype(np.float32)).cuda()
     gx = None
@@ -262,3 +262,38 @@ def test_backward_very_large_cells(oracle_mod):
     ew = _compare(gw, ow, sites)
     print("very large cells: %d of %d sites, max rel err %.2e / %.2e" % (len(sites), len(ids), e.max(), ew.max()))
     assert e.max() <= GRAD_TOL and ew.max() <= GRAD_TOL
+
+
+@pytest.mark.parametrize("name", ["uniform", "power_uniform"])
+def test_backward_with_box_of_the_sites(oracle_mod, name):
+    """No box given: the box is the sites' bounding box and its faces move
+    with the extreme sites, whose gradients then carry the faces' terms (the
+    oracle is pinned by finite differences that recompute that box)."""
+    from oracle import grad as og
+    n = 2000
+    xyz, w, _ = getattr(wl, name)(n, 8)
+    rng = np.random.default_rng(2)
+    g_vol = rng.normal(size=n) * n
+    g_cen = rng.normal(size=(n, 3))
+    d, gp, gw, _ = _run_backward(xyz, w, None, g_vol, g_cen, False)
+    op, ow, res = og.backward(xyz, w, None, g_vol, g_cen)
+    sites = _same_topology_sites(d, res, np.arange(n))
+    ext = np.unique(np.concatenate([xyz.argmin(0), xyz.argmax(0)]))
+    assert len(sites) >= 0.9 * n and set(ext.tolist()) <= set(sites.tolist())
+    e = _compare(gp, op, sites)
+    print("%s, box of the sites: %d sites, max rel err %.2e (extreme sites %.2e)"
+          % (name, len(sites), e.max(), _compare(gp, op, ext).max()))
+    assert e.max() <= GRAD_TOL
+    if w is not None:
+        assert _compare(gw, ow, sites).max() <= GRAD_TOL
+
+
+def test_vertex_gradient_must_cover_every_vertex():
+    import torch
+    import paper_2605_06408_amd as vd
+    xyz, w, box = wl.uniform(300, 1)
+    ctx = vd.Context(0)
+    d = ctx.build(torch.from_numpy(xyz).cuda(), None, bbox=[float(v) for v in box])
+    short = torch.zeros((d.sizes["n_vert"] - 1, 3), dtype=torch.float32, device="cuda")
+    with pytest.raises(ValueError):
+        ctx.backward(None, None, short)

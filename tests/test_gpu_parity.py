@@ -9,7 +9,7 @@ import pytest
 
 from paper_2605_06408_amd import workloads as wl
 
-from .parity import assert_parity, compare, gpu_build, to_numpy
+from .parity import TAU_FP32, TAU_MIXED, assert_parity, compare, gpu_build, to_numpy
 
 pytestmark = pytest.mark.gpu
 
@@ -251,13 +251,16 @@ def test_very_large_cells(oracle_mod, kind, precision):
     ids = np.unique(np.concatenate([np.arange(big), rng.choice(len(xyz), 1500, replace=False)]))
     g = to_numpy(d, ids)
     o = oracle_mod.cells(xyz, w, box, ids=ids)
-    assert_parity(compare(g, o), 0.8)
+    tau = TAU_FP32 if precision == 1 else TAU_MIXED
+    assert_parity(compare(g, o, tau=tau), 0.8)
     for t in range(big):
         gn = set(g["nbr"][g["nbr_off"][t]:g["nbr_off"][t + 1]].tolist())
         on = set(o["nbr"][o["nbr_off"][t]:o["nbr_off"][t + 1]].tolist())
         nv = int(g["vert_off"][t + 1] - g["vert_off"][t])
-        print("cell %d: %d vertices, %d neighbours, %d differ; volume %.9g vs %.9g"
-              % (t, nv, len(on), len(gn ^ on), g["vol"][t], o["vol"][t]))
+        print("cell %d: %d vertices, %d neighbours, %d differ; margin %.2e; volume %.9g vs %.9g"
+              % (t, nv, len(on), len(gn ^ on), o["margin"][t], g["vol"][t], o["vol"][t]))
+        # a certified cell matched exactly above; below the gate of the form
+        # (some vertex within its rounding of a foreign plane) nearly the same
         assert len(gn ^ on) <= max(2, len(on) // 100)
         assert abs(float(g["vol"][t]) - o["vol"][t]) <= 1e-5 * o["vol"][t]
         ext = float(np.ptp(o["vert"][o["vert_off"][t]:o["vert_off"][t + 1]], axis=0).max())

@@ -2,16 +2,18 @@
 form, each against the FP64 oracle, and the rate at which the mixed form
 re-evaluates vertex side tests in FP64.
 
-Both forms must be exact on certified cells (the parity bar); the report
-states, per form, the mismatch rate of uncertified cells (configurations FP32
-cannot decide, Sec. "Precision" of the supplement) and the largest geometry
-errors."""
+The plain FP32 form must be exact on cells certified at TAU_FP32 = 1e-5 and
+the mixed form on cells certified at TAU_MIXED = 1e-10 (its doubtful signs are
+decided in FP64, so only configurations within FP64 reach of a degeneracy
+remain undecided).  The report states, per form, the mismatch rate of the
+cells below its gate (configurations its arithmetic cannot decide, Sec.
+"Precision" of the supplement) and the p50 / p99 / max geometry errors."""
 import numpy as np
 import pytest
 
 from paper_2605_06408_amd import workloads as wl
 
-from .parity import compare, gpu_build, to_numpy
+from .parity import TAU_FP32, TAU_MIXED, compare, error_table, gpu_build, to_numpy
 
 pytestmark = pytest.mark.gpu
 
@@ -33,13 +35,13 @@ def _report(oracle_mod, name, n_sample, seed):
     out = {}
     for prec, d in rows.items():
         g = to_numpy(d, ids)
-        rep = compare(g, o)
+        rep = compare(g, o, tau=TAU_FP32 if prec == 1 else TAU_MIXED)
         out[prec] = rep
-        print("%s precision=%d: cells %d certified %d uncertified %d (mismatch %d) certified failures %d/%d "
-              "max err vert %.2e vol %.2e cen %.2e; whole build: fp64 cells %d uncertain %d"
-              % (name, prec, rep["cells"], rep["certified"], rep["uncertified"], rep["uncertified_mismatch"],
-                 len(rep["topo_fail"]), len(rep["geo_fail"]), rep["max_vert_err"], rep["max_vol_err"],
-                 rep["max_cen_err"], d.sizes["n_fp64"], d.sizes["n_uncertain"]))
+        print("%s precision=%d (gate %g): cells %d certified %d uncertified %d (mismatch %d) certified failures "
+              "%d/%d; whole build: fp64 cells %d uncertain %d; errors p50/p99/max %s"
+              % (name, prec, rep["tau"], rep["cells"], rep["certified"], rep["uncertified"],
+                 rep["uncertified_mismatch"], len(rep["topo_fail"]), len(rep["geo_fail"]), d.sizes["n_fp64"],
+                 d.sizes["n_uncertain"], error_table(rep)))
     del rows
     torch.cuda.empty_cache()
     return out
@@ -52,8 +54,12 @@ def test_fp32_and_mixed_against_oracle(oracle_mod, name, n_sample):
         rep = out[prec]
         assert not rep["topo_fail"] and not rep["geo_fail"], rep
         assert rep["max_vert_err"] <= 1e-5 and rep["max_vol_err"] <= 1e-5 and rep["max_cen_err"] <= 1e-5
-    # the FP64 re-evaluation decides doubtful signs the way the oracle does
-    assert out[2]["uncertified_mismatch"] <= out[1]["uncertified_mismatch"]
+    # below its gate each form may differ from the oracle, but rarely
+    for prec in (1, 2):
+        rep = out[prec]
+        assert rep["uncertified_mismatch"] <= max(3, 0.5 * rep["uncertified"]), rep["uncertified_mismatch"]
+    # the mixed form's gate covers at least the FP32 form's cells
+    assert out[2]["certified"] >= out[1]["certified"]
 
 
 @pytest.mark.parametrize("name", ["power_uniform_1m", "surface_20m"])

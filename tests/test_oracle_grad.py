@@ -126,3 +126,26 @@ def test_volume_weight_closed_form_on_random_power_diagram():
             expect[code] -= area / (2 * D)
             expect[i] += area / (2 * D)
         np.testing.assert_allclose(gw, expect, atol=1e-12)
+
+
+@pytest.mark.parametrize("weighted", [False, True])
+def test_gradient_with_box_of_the_sites(weighted):
+    """No clip box given: the box is the sites' bounding box, so moving an
+    extreme site moves a box face too.  Finite differences recompute that box
+    from the perturbed sites."""
+    xyz, w, g_vol, g_cen = _problem(20, 13 if weighted else 5, weighted)
+    gp, gw, res = og.backward(xyz, w, None, g_vol, g_cen, fp64=True)
+    assert not np.any(res["flags"] & 2), "test input must be in general position"
+    h = 1e-6
+    fp = np.zeros_like(gp)
+    for k in range(len(xyz)):
+        for c in range(3):
+            xp, xm = xyz.copy(), xyz.copy()
+            xp[k, c] += h
+            xm[k, c] -= h
+            fp[k, c] = (og.loss_value(xp, w, None, g_vol, g_cen) - og.loss_value(xm, w, None, g_vol, g_cen)) / (2 * h)
+    assert np.abs(gp - fp).max() <= 1e-6 * np.abs(fp).max()
+    # the box term matters here: with the box held fixed the extreme sites differ
+    gfix, _, _ = og.backward(xyz, w, np.concatenate([xyz.min(0), xyz.max(0)]), g_vol, g_cen, fp64=True)
+    ext = np.unique(np.concatenate([xyz.argmin(0), xyz.argmax(0)]))
+    assert np.abs(gfix[ext] - fp[ext]).max() > 1e-3 * np.abs(fp).max()

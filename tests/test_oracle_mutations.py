@@ -71,6 +71,7 @@ GRAD_MUTANTS = {
     "box_face_sign": ("add(i, -dB[c] * a, 0.0)", "add(i, dB[c] * a, 0.0)"),
     "transposed_solve": ("g = np.linalg.solve(M.T, gv[v])", "g = np.linalg.solve(M, gv[v])"),
     "pyramid_moment": ("integ[c][1] / (4.0 * np.linalg.norm", "integ[c][1] / (3.0 * np.linalg.norm"),
+    "moving_box_face_sign": ("gp[j, ax] += box_db[c] if side else -box_db[c]", "gp[j, ax] += box_db[c]"),
 }
 
 
