@@ -4,8 +4,9 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The product path (the HIP library and
 its Python binding) never imports it and shares no code with it.
 
-``cells()`` wraps ``liboracle.so`` (``vd_oracle.cpp``: FP64 brute-force
-clipping of the cell definition, paper Sec. 3 Eq. 1 and Sec. 4.1).
+``cells()`` wraps ``liboracle.so`` (``vd_oracle.cpp``: FP64 clipping of the
+cell definition, paper Sec. 3 Eq. 1 and Sec. 4.1, with candidates in
+increasing plane distance from brute force or a k-d tree).
 ``brute`` holds an exact-rational vertex enumeration used to pin the C++
 oracle on tiny inputs.  ``tetrahedra()`` reads the dual (regular / Delaunay)
 tetrahedra off the cells.
@@ -60,9 +61,10 @@ def _load():
         lib = ctypes.CDLL(_LIB_PATH)
         P = ctypes.c_void_p
         lib.orc_run.restype = P
-        lib.orc_run.argtypes = [P, P, ctypes.c_int64, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int]
+        lib.orc_run.argtypes = [P, P, ctypes.c_int64, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int]
         lib.orc_run64.restype = P
-        lib.orc_run64.argtypes = [P, P, ctypes.c_int64, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int]
+        lib.orc_run64.argtypes = [P, P, ctypes.c_int64, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                                  ctypes.c_int]
         lib.orc_sizes.restype = None
         lib.orc_sizes.argtypes = [P, P]
         lib.orc_fetch.restype = None
@@ -83,13 +85,19 @@ def default_box(xyz: np.ndarray) -> np.ndarray:
     return np.concatenate([x.min(axis=0), x.max(axis=0)]).astype(np.float64)
 
 
-def cells(xyz, w=None, box=None, ids=None, margin: bool = True, threads: int = 0, fp64: bool = False) -> dict:
+CANDIDATES = {"auto": 0, "brute": 1, "kdtree": 2}
+
+
+def cells(xyz, w=None, box=None, ids=None, margin: bool = True, threads: int = 0, fp64: bool = False,
+          candidates: str = "auto") -> dict:
     """Compute the cells ``ids`` (default: all) of the power diagram of
     (xyz, w) clipped to ``box`` = [xmin, ymin, zmin, xmax, ymax, zmax].
 
     By default sites, weights and box are FP32 values (as the library takes
     them).  ``fp64=True`` takes all three as FP64 values instead (finite
-    differences perturb inputs below FP32 resolution)."""
+    differences perturb inputs below FP32 resolution).  ``candidates``:
+    "brute" (every site), "kdtree" (best-first k-d tree walk) or "auto"
+    (brute force up to 20000 sites); both give bit-identical results."""
     lib = _load()
     dt = np.float64 if fp64 else np.float32
     xyz = np.ascontiguousarray(xyz, dtype=dt)
@@ -108,7 +116,7 @@ def cells(xyz, w=None, box=None, ids=None, margin: bool = True, threads: int = 0
     else:
         m = n
     run = lib.orc_run64 if fp64 else lib.orc_run
-    h = run(_ptr(xyz), _ptr(w), n, _ptr(box), _ptr(ids), m, int(margin), int(threads))
+    h = run(_ptr(xyz), _ptr(w), n, _ptr(box), _ptr(ids), m, int(margin), int(threads), CANDIDATES[candidates])
     if not h:
         raise ValueError("oracle rejected its input")
     try:

@@ -2,7 +2,8 @@
 //
 // Only tests/, the smoke check and the CPU-baseline leg of the benchmark may
 // load this library.  It shares no code with the GPU path and is deliberately
-// plain: FP64 arithmetic, brute-force candidate enumeration, O(V^2) clipping.
+// plain: FP64 arithmetic, candidates in increasing plane distance (brute force
+// or a k-d tree, same sequence), O(V^2) clipping.
 //
 // What it computes (paper, Sec. 3, Eq. 1): for site p_i with weight w_i,
 //     C_i = B  intersected with  { x : |x-p_i|^2 - w_i <= |x-p_j|^2 - w_j  for all j != i }
@@ -11,12 +12,19 @@
 // b_ij = (|a_ij|^2 + w_i - w_j) / 2;  b_ij / |a_ij| is the signed distance of
 // the bisecting (radical) plane from p_i (paper, Sec. 4.2, Eq. 2).
 //
-// Candidate enumeration: all j != i are sorted by that plane distance d_ij and
-// clipped in increasing order; once d_ij exceeds the largest vertex distance R
-// of the current cell no remaining plane can reach the cell, because every
-// point of the cell lies within R of p_i (this is the isotropic security
-// radius of Levy and Bonneel, which the paper cites as prior art in Sec. 4.2.1;
-// the paper's own directional BVH walk is what the GPU path implements).
+// Candidate enumeration: all j != i are taken in increasing plane distance
+// d_ij (ties: lower index first) and clipped in that order; once d_ij exceeds
+// the largest vertex distance R of the current cell no remaining plane can
+// reach the cell, because every point of the cell lies within R of p_i (this
+// is the isotropic security radius of Levy and Bonneel, which the paper cites
+// as prior art in Sec. 4.2.1; the paper's own directional BVH walk is what the
+// GPU path implements).  Two ways to produce that order: brute force (every
+// site's d_ij, partially sorted), or a best-first walk of a median-split k-d
+// tree whose nodes also hold the largest weight below them, keyed by the
+// lower bound d_B/2 + min(0, w_i - w_max)/(2 d_B) of d_ij over a node at
+// distance d_B (Sec. 4.2.2's bound with an isotropic radius).  The walk emits
+// exactly the brute-force sequence (a node is expanded before any site whose
+// d_ij is not below its key), so both modes give bit-identical results.
 //
 // Clipping (paper, Sec. 4.1 and supplementary Sec. B): vertices strictly on
 // the positive side of a_h.y - b_h are removed, zero is kept; each new vertex
@@ -109,6 +117,7 @@ struct Input {
     int64_t n;
     double box[6];   // lo.xyz, hi.xyz
     std::vector<char> loser;  // coincident site whose cell is empty
+    std::vector<char> twin;   // some other site has the same position
 };
 
 inline double site_w(const Input& in, int64_t j) { return in.w ? (double)in.w[j] : 0.0; }
@@ -231,35 +240,203 @@ struct CellOut {
     std::vector<int64_t> fv;      // cell-local vertex indices, CCW seen from outside
 };
 
-// Enumerate candidates for site i in increasing plane distance and clip until
-// no further plane can reach the cell.  Returns the number of candidates
-// examined (those with d <= reach are left at the front of `cand`).
+// Median-split k-d tree over the sites (leaves of at most kKdLeaf sites);
+// every node stores the bounding box and the largest weight of its sites.
+constexpr int kKdLeaf = 8;
+struct KdNode {
+    double lo[3], hi[3];
+    double wmax;
+    int64_t begin, end;   // range of `perm`
+    int64_t left, right;  // children (-1: leaf)
+};
+struct KdTree {
+    std::vector<KdNode> nodes;
+    std::vector<int64_t> perm;
+};
+
+// Builds the subtree over perm[b, e) and returns its node index.  Large
+// ranges build their two halves as OpenMP tasks (the tree and the input are
+// passed by pointer, which a task copies as a plain value).
+int64_t kd_build_range(const Input* in, KdTree* T, int64_t b, int64_t e) {
+    KdNode nd;
+    for (int k = 0; k < 3; ++k) {
+        nd.lo[k] = INFINITY;
+        nd.hi[k] = -INFINITY;
+    }
+    nd.wmax = -INFINITY;
+    for (int64_t q = b; q < e; ++q) {
+        const int64_t j = T->perm[(size_t)q];
+        for (int k = 0; k < 3; ++k) {
+            nd.lo[k] = std::min(nd.lo[k], in->xyz[3 * j + k]);
+            nd.hi[k] = std::max(nd.hi[k], in->xyz[3 * j + k]);
+        }
+        nd.wmax = std::max(nd.wmax, site_w(*in, j));
+    }
+    nd.begin = b;
+    nd.end = e;
+    nd.left = nd.right = -1;
+    int64_t id;
+#pragma omp critical(kd_nodes)
+    {
+        id = (int64_t)T->nodes.size();
+        T->nodes.push_back(nd);
+    }
+    if (e - b <= kKdLeaf) return id;
+    int ax = 0;
+    for (int k = 1; k < 3; ++k)
+        if (nd.hi[k] - nd.lo[k] > nd.hi[ax] - nd.lo[ax]) ax = k;
+    const int64_t mid = b + (e - b) / 2;
+    const double* xyz = in->xyz;
+    std::nth_element(T->perm.begin() + b, T->perm.begin() + mid, T->perm.begin() + e,
+                     [xyz, ax](int64_t x, int64_t y) { return xyz[3 * x + ax] < xyz[3 * y + ax]; });
+    int64_t l = -1, r = -1;
+    if (e - b > 65536) {
+#pragma omp task shared(l) firstprivate(in, T, b, mid)
+        l = kd_build_range(in, T, b, mid);
+#pragma omp task shared(r) firstprivate(in, T, mid, e)
+        r = kd_build_range(in, T, mid, e);
+#pragma omp taskwait
+    } else {
+        l = kd_build_range(in, T, b, mid);
+        r = kd_build_range(in, T, mid, e);
+    }
+#pragma omp critical(kd_nodes)
+    {
+        T->nodes[(size_t)id].left = l;
+        T->nodes[(size_t)id].right = r;
+    }
+    return id;
+}
+
+void kd_build(const Input& in, KdTree& T) {
+    T.perm.resize((size_t)in.n);
+    for (int64_t j = 0; j < in.n; ++j) T.perm[(size_t)j] = j;
+    T.nodes.reserve((size_t)(4 * in.n / kKdLeaf + 16));
+    const Input* ip = &in;
+    KdTree* tp = &T;
+#pragma omp parallel
+#pragma omp single
+    kd_build_range(ip, tp, 0, in.n);
+}
+
+// Distance from p to a node's box.
+double box_distance(const KdNode& nd, const double* p) {
+    double d2 = 0;
+    for (int k = 0; k < 3; ++k) {
+        const double t = std::max(std::max(nd.lo[k] - p[k], p[k] - nd.hi[k]), 0.0);
+        d2 += t * t;
+    }
+    return std::sqrt(d2);
+}
+
+// Lower bound, over the sites j of a node at distance dB from p_i, of
+// (|a|^2 (1 - tau) + g(w_i - w_j)) / (2 |a|) with g(x) = x (1 - tau) for x >= 0
+// and x (1 + tau) below; tau = 0 gives the plane distance d_ij.  The function
+// of t = |a| >= dB is t (1 - tau)/2 + g/(2t), increasing when g < 0, and g is
+// increasing in w_i - w_j >= w_i - w_max.  Rounded down by a relative margin
+// far above FP64 rounding, so that the key never exceeds a computed d_ij.
+double node_key(const KdNode& nd, const double* p, double wi, double tau) {
+    const double dB = box_distance(nd, p);
+    const double c = std::min(0.0, wi - nd.wmax) * (1.0 + tau);
+    double lb;
+    if (c < 0.0) lb = dB > 0.0 ? 0.5 * dB * (1.0 - tau) + c / (2.0 * dB) : -INFINITY;
+    else lb = 0.5 * dB * (1.0 - tau);
+    return lb - 1e-9 * std::fabs(lb);
+}
+
+// Candidates for site i in increasing plane distance (ties: lower index).
 struct Builder {
     const Input& in;
+    const KdTree* kd;  // null: brute force
+    int64_t i = -1;
+    double p[3] = {0, 0, 0}, wi = 0;
+    // brute force: every candidate, sorted lazily
     std::vector<Cand> cand;
-    size_t sorted_upto = 0;
+    size_t sorted_upto = 0, pos = 0;
+    // k-d tree: heap of nodes (kind 0) and sites (kind 1)
+    struct Entry {
+        double key;
+        int kind;
+        int64_t id;
+    };
+    std::vector<Entry> heap;
 
-    explicit Builder(const Input& input) : in(input) {}
+    Builder(const Input& input, const KdTree* tree) : in(input), kd(tree) {}
 
-    // Fill `cand` with all j != i except coincident losers.  Returns false
-    // if site i itself is a coincident loser (empty cell).
-    bool gather(int64_t i, bool& coincident) {
+    static bool after(const Entry& x, const Entry& y) {  // heap order: smallest (key, kind, id) on top
+        if (x.key != y.key) return x.key > y.key;
+        if (x.kind != y.kind) return x.kind > y.kind;
+        return x.id > y.id;
+    }
+
+    // Plane distance of candidate j (the same expression in both modes).
+    double dist_of(int64_t j, double* d2out) const {
+        const double ax = in.xyz[3 * j] - p[0], ay = in.xyz[3 * j + 1] - p[1], az = in.xyz[3 * j + 2] - p[2];
+        const double d2 = ax * ax + ay * ay + az * az;
+        *d2out = d2;
+        return (d2 + (wi - site_w(in, j))) / (2.0 * std::sqrt(d2));
+    }
+
+    // Start the enumeration for site i.  Returns false if site i is a
+    // coincident loser (empty cell); `coincident` tells whether some other
+    // site has the same position.
+    bool start(int64_t site, bool& coincident) {
+        i = site;
+        for (int k = 0; k < 3; ++k) p[k] = in.xyz[3 * i + k];
+        wi = site_w(in, i);
+        coincident = in.twin[(size_t)i] != 0;
         cand.clear();
-        sorted_upto = 0;
-        coincident = false;
-        const double wi = site_w(in, i);
-        const double px = in.xyz[3 * i], py = in.xyz[3 * i + 1], pz = in.xyz[3 * i + 2];
-        for (int64_t j = 0; j < in.n; ++j) {
-            if (j == i) continue;
-            double ax = (double)in.xyz[3 * j] - px, ay = (double)in.xyz[3 * j + 1] - py,
-                   az = (double)in.xyz[3 * j + 2] - pz;
-            double d2 = ax * ax + ay * ay + az * az;
-            if (d2 == 0.0) coincident = true;
-            if (in.loser[j] || d2 == 0.0) continue;
-            double D = std::sqrt(d2);
-            cand.push_back({(d2 + (wi - site_w(in, j))) / (2.0 * D), j});
+        heap.clear();
+        sorted_upto = pos = 0;
+        if (!kd) {
+            for (int64_t j = 0; j < in.n; ++j) {
+                if (j == i || in.loser[(size_t)j]) continue;
+                double d2;
+                const double d = dist_of(j, &d2);
+                if (d2 == 0.0) continue;
+                cand.push_back({d, j});
+            }
+        } else {
+            heap.push_back({node_key(kd->nodes[0], p, wi, 0.0), 0, 0});
         }
-        return !in.loser[i];
+        return !in.loser[(size_t)i];
+    }
+
+    // The next candidate; false when none is left.
+    bool next(Cand& c) {
+        if (!kd) {
+            ensure_sorted(pos + 1);
+            if (pos >= cand.size()) return false;
+            c = cand[pos++];
+            return true;
+        }
+        while (!heap.empty()) {
+            std::pop_heap(heap.begin(), heap.end(), after);
+            const Entry e = heap.back();
+            heap.pop_back();
+            if (e.kind == 1) {
+                c = {e.key, e.id};
+                return true;
+            }
+            const KdNode& nd = kd->nodes[(size_t)e.id];
+            if (nd.left < 0) {
+                for (int64_t q = nd.begin; q < nd.end; ++q) {
+                    const int64_t j = kd->perm[(size_t)q];
+                    if (j == i || in.loser[(size_t)j]) continue;
+                    double d2;
+                    const double d = dist_of(j, &d2);
+                    if (d2 == 0.0) continue;
+                    heap.push_back({d, 1, j});
+                    std::push_heap(heap.begin(), heap.end(), after);
+                }
+            } else {
+                for (int64_t ch : {nd.left, nd.right}) {
+                    heap.push_back({node_key(kd->nodes[(size_t)ch], p, wi, 0.0), 0, ch});
+                    std::push_heap(heap.begin(), heap.end(), after);
+                }
+            }
+        }
+        return false;
     }
 
     // Make sure cand[0 .. k) is sorted and holds the k smallest distances.
@@ -270,6 +447,69 @@ struct Builder {
         auto less = [](const Cand& x, const Cand& y) { return x.d < y.d || (x.d == y.d && x.j < y.j); };
         std::partial_sort(cand.begin() + sorted_upto, cand.begin() + want, cand.end(), less);
         sorted_upto = want;
+    }
+
+    // Calls f(candidate) for every candidate j (all of them in brute force);
+    // with the k-d tree at least for every j whose
+    // d_ij - tau sig_ij < T (sig_ij = (|a|^2 + |w_i - w_j|) / (2 |a|)).
+    template <typename F>
+    void for_each(double T, double tau, F f) {
+        if (!kd) {
+            for (const Cand& c : cand) f(c);
+            return;
+        }
+        const double Tr = T + 1e-6 * std::fabs(T);
+        std::vector<int64_t> stack{0};
+        while (!stack.empty()) {
+            const KdNode& nd = kd->nodes[(size_t)stack.back()];
+            stack.pop_back();
+            if (node_key(nd, p, wi, tau) >= Tr) continue;
+            if (nd.left >= 0) {
+                stack.push_back(nd.left);
+                stack.push_back(nd.right);
+                continue;
+            }
+            for (int64_t q = nd.begin; q < nd.end; ++q) {
+                const int64_t j = kd->perm[(size_t)q];
+                if (j == i || in.loser[(size_t)j]) continue;
+                double d2;
+                const double d = dist_of(j, &d2);
+                if (d2 == 0.0) continue;
+                f(Cand{d, j});
+            }
+        }
+    }
+
+    // Smallest distance |p_j - p_i| to another (non-coincident, non-loser) site.
+    double nearest() {
+        double best2 = INFINITY;
+        auto consider = [&](int64_t j) {
+            if (j == i || in.loser[(size_t)j]) return;
+            double d2;
+            dist_of(j, &d2);
+            if (d2 != 0.0) best2 = std::min(best2, d2);
+        };
+        if (!kd) {
+            for (const Cand& c : cand) consider(c.j);
+            return std::sqrt(best2);
+        }
+        std::vector<std::pair<double, int64_t>> pq{{0.0, 0}};
+        while (!pq.empty()) {
+            std::pop_heap(pq.begin(), pq.end(), std::greater<>());
+            const auto e = pq.back();
+            pq.pop_back();
+            if (e.first * e.first > best2) break;
+            const KdNode& nd = kd->nodes[(size_t)e.second];
+            if (nd.left < 0) {
+                for (int64_t q = nd.begin; q < nd.end; ++q) consider(kd->perm[(size_t)q]);
+            } else {
+                for (int64_t ch : {nd.left, nd.right}) {
+                    pq.push_back({box_distance(kd->nodes[(size_t)ch], p), ch});
+                    std::push_heap(pq.begin(), pq.end(), std::greater<>());
+                }
+            }
+        }
+        return std::sqrt(best2);
     }
 };
 
@@ -285,7 +525,7 @@ size_t build_poly(const Input& in, Builder& B, int64_t i, double wshift, Poly& P
     double p[3] = {(double)in.xyz[3 * i], (double)in.xyz[3 * i + 1], (double)in.xyz[3 * i + 2]};
     init_box(P, p, in.box);
     bool coincident = false;
-    bool alive = B.gather(i, coincident);
+    bool alive = B.start(i, coincident);
     if (coincident) flags |= OF_COINCIDENT;
     if (!alive) {
         P.empty = true;
@@ -294,13 +534,13 @@ size_t build_poly(const Input& in, Builder& B, int64_t i, double wshift, Poly& P
     }
     size_t t = 0;
     double R = max_radius(P);
+    Cand c;
     for (;; ++t) {
-        B.ensure_sorted(t + 1);
-        if (t >= B.cand.size()) break;
+        if (!B.next(c)) break;
         // a weight raised by wshift >= 0 only moves planes outward (by
         // wshift / (2 D)), so the unshifted order still bounds the rest
-        if (B.cand[t].d > R) break;
-        Plane h = make_plane(in, i, B.cand[t].j);
+        if (c.d > R) break;
+        Plane h = make_plane(in, i, c.j);
         h.b += 0.5 * wshift;
         if (clip(P, h)) {
             if (P.empty) break;
@@ -364,15 +604,17 @@ double margin_of_cell(const Input& in, Builder& B, int64_t i, const Poly& P) {
     Poly boxp;
     init_box(boxp, p, in.box);
     for (const Plane& h : boxp.pl) visit(h);
-    for (const Cand& c : B.cand) {
+    // (the k-d tree enumerates every candidate with d - tau_m sig below
+    // R + tau_m (emax + R), which includes every one not skipped here)
+    B.for_each(R + tau_m * (emax + R), tau_m, [&](const Cand& c) {
         if (c.d - R > tau_m * (emax + R)) {
             Plane h = make_plane(in, i, c.j);
-            if (c.d - R >= tau_m * (emax + R + h.sig)) continue;
+            if (c.d - R >= tau_m * (emax + R + h.sig)) return;
             visit(h);
         } else {
             visit(make_plane(in, i, c.j));
         }
-    }
+    });
     return std::max(margin, 0.0);
 }
 
@@ -500,51 +742,47 @@ struct Result {
     std::vector<CellOut> cells;
 };
 
-double nearest_distance(const Input& in, const Builder& B, int64_t i) {
-    // smallest Euclidean distance to another (non-coincident) site
-    double best = INFINITY;
-    for (const Cand& c : B.cand) {
-        Plane h = make_plane(in, i, c.j);
-        best = std::min(best, norm3(h.a));
-    }
-    return best;
-}
-
 }  // namespace
 
 extern "C" {
 
 static void* run_impl(const double* xyz, const double* w, int64_t n, const double* box, const int64_t* cells, int64_t m,
-                     int want_margin, int nthreads);
+                     int want_margin, int nthreads, int mode);
 
 // Compute cells `cells[0..m)` (all n cells if cells == NULL).  `box` is
 // [lo.xyz, hi.xyz] in FP64.  Returns an opaque handle, or NULL on bad input.
-// `want_margin` = 0 skips the robustness margin (faster).
+// `want_margin` = 0 skips the robustness margin (faster).  `mode`: candidate
+// enumeration, 1 brute force, 2 k-d tree, 0 brute force up to 20000 sites and
+// the k-d tree above (the results are identical).
 void* orc_run(const float* xyz, const float* w, int64_t n, const double* box, const int64_t* cells, int64_t m,
-              int want_margin, int nthreads) {
-    if (n <= 0 || !xyz || !box) return nullptr;
+              int want_margin, int nthreads, int mode) {
+    if (n <= 0 || !xyz || !box || mode < 0 || mode > 2) return nullptr;
     std::vector<double> x((size_t)(3 * n)), ww;
     for (int64_t k = 0; k < 3 * n; ++k) x[(size_t)k] = (double)xyz[k];
     if (w) {
         ww.resize((size_t)n);
         for (int64_t k = 0; k < n; ++k) ww[(size_t)k] = (double)w[k];
     }
-    return run_impl(x.data(), w ? ww.data() : nullptr, n, box, cells, m, want_margin, nthreads);
+    return run_impl(x.data(), w ? ww.data() : nullptr, n, box, cells, m, want_margin, nthreads, mode);
 }
 
 // The same with FP64 sites and weights.
 void* orc_run64(const double* xyz, const double* w, int64_t n, const double* box, const int64_t* cells, int64_t m,
-                int want_margin, int nthreads) {
-    if (n <= 0 || !xyz || !box) return nullptr;
-    return run_impl(xyz, w, n, box, cells, m, want_margin, nthreads);
+                int want_margin, int nthreads, int mode) {
+    if (n <= 0 || !xyz || !box || mode < 0 || mode > 2) return nullptr;
+    return run_impl(xyz, w, n, box, cells, m, want_margin, nthreads, mode);
 }
 
 static void* run_impl(const double* xyz, const double* w, int64_t n, const double* box, const int64_t* cells, int64_t m,
-                     int want_margin, int nthreads) {
-    Input in{xyz, w, n, {box[0], box[1], box[2], box[3], box[4], box[5]}, {}};
+                     int want_margin, int nthreads, int mode) {
+    Input in{xyz, w, n, {box[0], box[1], box[2], box[3], box[4], box[5]}, {}, {}};
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
     // coincident sites: sort by position, the heaviest of each run of equal
     // positions (lowest index among equals) is the only one that keeps a cell
     in.loser.assign((size_t)n, 0);
+    in.twin.assign((size_t)n, 0);
     {
         std::vector<int64_t> ord((size_t)n);
         for (int64_t k = 0; k < n; ++k) ord[(size_t)k] = k;
@@ -560,6 +798,7 @@ static void* run_impl(const double* xyz, const double* w, int64_t n, const doubl
                    xyz[3 * ord[b] + 2] == xyz[3 * ord[a] + 2])
                 ++b;
             if (b - a > 1) {
+                for (size_t t = a; t < b; ++t) in.twin[(size_t)ord[t]] = 1;
                 size_t win = a;
                 for (size_t t = a + 1; t < b; ++t) {
                     double wt = w ? (double)w[ord[t]] : 0.0, ww = w ? (double)w[ord[win]] : 0.0;
@@ -571,15 +810,15 @@ static void* run_impl(const double* xyz, const double* w, int64_t n, const doubl
             a = b;
         }
     }
+    KdTree tree;
+    const bool use_kd = mode == 2 || (mode == 0 && n > 20000);
+    if (use_kd) kd_build(in, tree);
     Result* res = new Result;
     const int64_t count = cells ? m : n;
     res->cells.resize((size_t)count);
-#ifdef _OPENMP
-    if (nthreads > 0) omp_set_num_threads(nthreads);
-#endif
 #pragma omp parallel
     {
-        Builder B(in);
+        Builder B(in, use_kd ? &tree : nullptr);
         Poly P;
 #pragma omp for schedule(dynamic, 4)
         for (int64_t t = 0; t < count; ++t) {
@@ -596,7 +835,7 @@ static void* run_impl(const double* xyz, const double* w, int64_t n, const doubl
                 } else if (out.flags & OF_EMPTY) {
                     // robustly empty at level tau: still empty after raising
                     // w_i by tau (l^2 + |w_i|), l = nearest-site distance
-                    double l = nearest_distance(in, B, i);
+                    double l = B.nearest();
                     if (!std::isfinite(l)) l = 0;
                     out.margin = 0.0;
                     const double levels[4] = {1e-3, 1e-5, 1e-7, 1e-10};

@@ -33,7 +33,7 @@ MUTANTS = {
     "centroid_weight": ("mom[r] += det * (a0[r] + a1[r] + a2[r]) / 4.0;",
                         "mom[r] += det * (a0[r] + a1[r] + a2[r]) / 3.0;"),
     "clockwise_facets": ("std::sort(ang.begin(), ang.end());", "std::sort(ang.rbegin(), ang.rend());"),
-    "early_stop": ("if (B.cand[t].d > R) break;", "if (B.cand[t].d > 0.7 * R) break;"),
+    "early_stop": ("if (c.d > R) break;", "if (c.d > 0.7 * R) break;"),
     "coincident_tie": ("if (wt > ww || (wt == ww && ord[t] < ord[win])) win = t;",
                        "if (wt > ww || (wt == ww && ord[t] > ord[win])) win = t;"),
     "squared_radius": ("return std::sqrt(r2);\n}", "return r2;\n}"),
@@ -152,3 +152,32 @@ def test_planted_margin_mistake_is_caught(name, tmp_path):
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=str(tmp_path),
                        timeout=600)
     assert r.returncode == 1, "mutant %s survived the margin pins:\n%s" % (name, r.stdout[-2000:])
+
+
+# Mistakes in the k-d tree candidate mode (its node key must never exceed
+# the plane distance of a site below the node).
+KD_MUTANTS = {
+    "node_key_ignores_weights": ("const double c = std::min(0.0, wi - nd.wmax) * (1.0 + tau);",
+                                 "const double c = 0.0;"),
+    "node_key_full_distance": ("else lb = 0.5 * dB * (1.0 - tau);", "else lb = dB * (1.0 - tau);"),
+}
+
+
+@pytest.mark.parametrize("name", sorted(KD_MUTANTS))
+def test_planted_kdtree_mistake_is_caught(name, tmp_path):
+    src = open(os.path.join(ROOT, "oracle", "vd_oracle.cpp")).read()
+    old, new = KD_MUTANTS[name]
+    assert src.count(old) == 1, "mutation site moved"
+    pkg = tmp_path / "oracle"
+    pkg.mkdir()
+    for f in ("__init__.py", "brute.py", "grad.py"):
+        shutil.copy(os.path.join(ROOT, "oracle", f), pkg / f)
+    (pkg / "vd_oracle.cpp").write_text(src.replace(old, new))
+    subprocess.run(["g++", "-O1", "-std=c++17", "-fopenmp", "-fPIC", "-shared", "-o",
+                    str(pkg / "liboracle.so"), str(pkg / "vd_oracle.cpp")], check=True)
+    code = ("import sys; sys.path.insert(0, %r); sys.path.insert(1, %r); import pytest; "
+            "sys.exit(pytest.main(['-q', '-x', '-p', 'no:cacheprovider', '--import-mode=append', %r]))"
+            % (str(tmp_path), ROOT, os.path.join(ROOT, "tests", "test_oracle_kdtree.py")))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=str(tmp_path),
+                       timeout=600)
+    assert r.returncode == 1, "mutant %s survived the k-d tree tests:\n%s" % (name, r.stdout[-2000:])
