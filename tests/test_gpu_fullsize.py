@@ -13,7 +13,9 @@ from .parity import assert_parity, compare, gpu_build, to_numpy
 pytestmark = pytest.mark.gpu
 
 
-def _sample(d, n, rng, k_random=200, k_large=60, k_empty=20):
+def _sample(d, n, rng, k_random, k_large, k_empty):
+    """Random cells, cells of the larger-capacity passes (all of them up to
+    k_large) and empty cells; the oracle's k-d tree mode makes each cheap."""
     flags = d.flags.cpu().numpy()
     ids = set(rng.choice(n, min(n, k_random), replace=False).tolist())
     large = np.nonzero(flags & 4)[0]
@@ -22,7 +24,7 @@ def _sample(d, n, rng, k_random=200, k_large=60, k_empty=20):
     empty = np.nonzero(flags & 1)[0]
     if len(empty):
         ids |= set(rng.choice(empty, min(len(empty), k_empty), replace=False).tolist())
-    return np.array(sorted(ids), np.int64)
+    return np.array(sorted(ids), np.int64), len(large)
 
 
 def _invariants(oracle_mod, d, xyz, w, box, tau=1e-5):
@@ -51,26 +53,33 @@ def _invariants(oracle_mod, d, xyz, w, box, tau=1e-5):
     assert d.sizes["n_failed"] == 0
 
 
+@pytest.mark.parametrize("seed", [0, 1, 2])
 @pytest.mark.parametrize("name", ["clustered_1m", "power_uniform_1m", "power_clustered_1m"])
-def test_one_million(oracle_mod, name):
-    xyz, w, box = wl.make(name, 0)
+def test_one_million(oracle_mod, name, seed):
+    xyz, w, box = wl.make(name, seed)
     d = gpu_build(xyz, w, box)
     _invariants(oracle_mod, d, xyz, w, box)
-    ids = _sample(d, len(xyz), np.random.default_rng(1))
+    ids, n_large = _sample(d, len(xyz), np.random.default_rng(1 + seed), k_random=20000, k_large=20000,
+                           k_empty=500)
     g = to_numpy(d, ids)
     o = oracle_mod.cells(xyz, w, box, ids=ids)
     rep = compare(g, o)
     rep["sizes"] = d.sizes
+    print("%s seed %d: %d cells compared (%d of the larger passes, of %d)"
+          % (name, seed, len(ids), int(((g["flags"] & 4) != 0).sum()), n_large))
     assert_parity(rep, 0.8)
 
 
-def test_surface_twenty_million(oracle_mod):
-    xyz, w, box = wl.make("surface_20m", 0)
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_surface_twenty_million(oracle_mod, seed):
+    xyz, w, box = wl.make("surface_20m", seed)
     d = gpu_build(xyz, w, box)
     _invariants(oracle_mod, d, xyz, w, box)
-    ids = _sample(d, len(xyz), np.random.default_rng(2), k_random=120, k_large=40, k_empty=0)
+    ids, n_large = _sample(d, len(xyz), np.random.default_rng(2 + seed), k_random=5000, k_large=5000, k_empty=0)
     g = to_numpy(d, ids)
     o = oracle_mod.cells(xyz, w, box, ids=ids)
     rep = compare(g, o)
     rep["sizes"] = d.sizes
+    print("surface_20m seed %d: %d cells compared (%d of the larger passes, of %d)"
+          % (seed, len(ids), int(((g["flags"] & 4) != 0).sum()), n_large))
     assert_parity(rep, 0.8)
