@@ -65,6 +65,12 @@ def _load():
         lib.orc_run64.restype = P
         lib.orc_run64.argtypes = [P, P, ctypes.c_int64, P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_int]
+        lib.orc_session_open.restype = P
+        lib.orc_session_open.argtypes = [P, P, ctypes.c_int64, P, ctypes.c_int, ctypes.c_int]
+        lib.orc_session_cells.restype = P
+        lib.orc_session_cells.argtypes = [P, P, ctypes.c_int64, ctypes.c_int, ctypes.c_int64, P]
+        lib.orc_session_close.restype = None
+        lib.orc_session_close.argtypes = [P]
         lib.orc_sizes.restype = None
         lib.orc_sizes.argtypes = [P, P]
         lib.orc_fetch.restype = None
@@ -117,6 +123,12 @@ def cells(xyz, w=None, box=None, ids=None, margin: bool = True, threads: int = 0
         m = n
     run = lib.orc_run64 if fp64 else lib.orc_run
     h = run(_ptr(xyz), _ptr(w), n, _ptr(box), _ptr(ids), m, int(margin), int(threads), CANDIDATES[candidates])
+    return _fetch(h, m, n, ids)
+
+
+def _fetch(h, m, n, ids):
+    """Copy a result handle into numpy arrays and free it."""
+    lib = _load()
     if not h:
         raise ValueError("oracle rejected its input")
     try:
@@ -138,6 +150,47 @@ def cells(xyz, w=None, box=None, ids=None, margin: bool = True, threads: int = 0
         lib.orc_free(h)
     out["ids"] = np.arange(n, dtype=np.int64) if ids is None else ids
     return out
+
+
+class Session:
+    """The oracle over one FP64 input kept across calls (with its k-d tree),
+    for finite differences: ``cells(ids, moved=(k, xyz_k, w_k))`` computes
+    cells with site k moved (and puts it back).  Results as ``cells()``."""
+
+    def __init__(self, xyz, w=None, box=None, threads: int = 0, candidates: str = "auto"):
+        lib = _load()
+        self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        self.n = self.xyz.shape[0]
+        self.w = None if w is None else np.ascontiguousarray(w, dtype=np.float64)
+        if box is None:
+            box = np.concatenate([self.xyz.min(axis=0), self.xyz.max(axis=0)])
+        self.box = np.asarray(box, dtype=np.float64)
+        self.h = lib.orc_session_open(_ptr(self.xyz), _ptr(self.w), self.n, _ptr(self.box), int(threads),
+                                      CANDIDATES[candidates])
+        if not self.h:
+            raise ValueError("oracle rejected its input")
+
+    def cells(self, ids, margin: bool = False, moved=None) -> dict:
+        ids = np.ascontiguousarray(ids, dtype=np.int64)
+        k, mv = -1, None
+        if moved is not None:
+            k = int(moved[0])
+            mv = np.zeros(4, np.float64)
+            mv[:3] = moved[1]
+            mv[3] = 0.0 if moved[2] is None else float(moved[2])
+        h = _load().orc_session_cells(self.h, _ptr(ids), len(ids), int(margin), k, _ptr(mv))
+        return _fetch(h, len(ids), self.n, ids)
+
+    def close(self):
+        if getattr(self, "h", None):
+            _load().orc_session_close(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def tetrahedra(res: dict) -> np.ndarray:

@@ -118,6 +118,7 @@ struct Input {
     double box[6];   // lo.xyz, hi.xyz
     std::vector<char> loser;  // coincident site whose cell is empty
     std::vector<char> twin;   // some other site has the same position
+    int64_t moved = -1;       // a site moved since the k-d tree was built (or -1)
 };
 
 inline double site_w(const Input& in, int64_t j) { return in.w ? (double)in.w[j] : 0.0; }
@@ -398,6 +399,14 @@ struct Builder {
             }
         } else {
             heap.push_back({node_key(kd->nodes[0], p, wi, 0.0), 0, 0});
+            // a moved site may lie outside the node boxes: it is a candidate of its own
+            const int64_t mv = in.moved;
+            if (mv >= 0 && mv != i && !in.loser[(size_t)mv]) {
+                double d2;
+                const double d = dist_of(mv, &d2);
+                if (d2 != 0.0) heap.push_back({d, 1, mv});
+                std::push_heap(heap.begin(), heap.end(), after);
+            }
         }
         return !in.loser[(size_t)i];
     }
@@ -422,7 +431,7 @@ struct Builder {
             if (nd.left < 0) {
                 for (int64_t q = nd.begin; q < nd.end; ++q) {
                     const int64_t j = kd->perm[(size_t)q];
-                    if (j == i || in.loser[(size_t)j]) continue;
+                    if (j == i || in.loser[(size_t)j] || j == in.moved) continue;
                     double d2;
                     const double d = dist_of(j, &d2);
                     if (d2 == 0.0) continue;
@@ -471,12 +480,18 @@ struct Builder {
             }
             for (int64_t q = nd.begin; q < nd.end; ++q) {
                 const int64_t j = kd->perm[(size_t)q];
-                if (j == i || in.loser[(size_t)j]) continue;
+                if (j == i || in.loser[(size_t)j] || j == in.moved) continue;
                 double d2;
                 const double d = dist_of(j, &d2);
                 if (d2 == 0.0) continue;
                 f(Cand{d, j});
             }
+        }
+        const int64_t mv = in.moved;
+        if (mv >= 0 && mv != i && !in.loser[(size_t)mv]) {
+            double d2;
+            const double d = dist_of(mv, &d2);
+            if (d2 != 0.0) f(Cand{d, mv});
         }
     }
 
@@ -493,6 +508,7 @@ struct Builder {
             for (const Cand& c : cand) consider(c.j);
             return std::sqrt(best2);
         }
+        if (in.moved >= 0) consider(in.moved);
         std::vector<std::pair<double, int64_t>> pq{{0.0, 0}};
         while (!pq.empty()) {
             std::pop_heap(pq.begin(), pq.end(), std::greater<>());
@@ -501,7 +517,8 @@ struct Builder {
             if (e.first * e.first > best2) break;
             const KdNode& nd = kd->nodes[(size_t)e.second];
             if (nd.left < 0) {
-                for (int64_t q = nd.begin; q < nd.end; ++q) consider(kd->perm[(size_t)q]);
+                for (int64_t q = nd.begin; q < nd.end; ++q)
+                    if (kd->perm[(size_t)q] != in.moved) consider(kd->perm[(size_t)q]);
             } else {
                 for (int64_t ch : {nd.left, nd.right}) {
                     pq.push_back({box_distance(kd->nodes[(size_t)ch], p), ch});
@@ -742,47 +759,31 @@ struct Result {
     std::vector<CellOut> cells;
 };
 
-}  // namespace
+// Everything the cells of one input share: FP64 copies of the sites and
+// weights, the coincident-site marks, and the k-d tree (when used).
+struct Session {
+    std::vector<double> xyz, w;
+    Input in;
+    KdTree tree;
+    bool use_kd = false;
+};
 
-extern "C" {
-
-static void* run_impl(const double* xyz, const double* w, int64_t n, const double* box, const int64_t* cells, int64_t m,
-                     int want_margin, int nthreads, int mode);
-
-// Compute cells `cells[0..m)` (all n cells if cells == NULL).  `box` is
-// [lo.xyz, hi.xyz] in FP64.  Returns an opaque handle, or NULL on bad input.
-// `want_margin` = 0 skips the robustness margin (faster).  `mode`: candidate
-// enumeration, 1 brute force, 2 k-d tree, 0 brute force up to 20000 sites and
-// the k-d tree above (the results are identical).
-void* orc_run(const float* xyz, const float* w, int64_t n, const double* box, const int64_t* cells, int64_t m,
-              int want_margin, int nthreads, int mode) {
-    if (n <= 0 || !xyz || !box || mode < 0 || mode > 2) return nullptr;
-    std::vector<double> x((size_t)(3 * n)), ww;
-    for (int64_t k = 0; k < 3 * n; ++k) x[(size_t)k] = (double)xyz[k];
-    if (w) {
-        ww.resize((size_t)n);
-        for (int64_t k = 0; k < n; ++k) ww[(size_t)k] = (double)w[k];
-    }
-    return run_impl(x.data(), w ? ww.data() : nullptr, n, box, cells, m, want_margin, nthreads, mode);
-}
-
-// The same with FP64 sites and weights.
-void* orc_run64(const double* xyz, const double* w, int64_t n, const double* box, const int64_t* cells, int64_t m,
-                int want_margin, int nthreads, int mode) {
-    if (n <= 0 || !xyz || !box || mode < 0 || mode > 2) return nullptr;
-    return run_impl(xyz, w, n, box, cells, m, want_margin, nthreads, mode);
-}
-
-static void* run_impl(const double* xyz, const double* w, int64_t n, const double* box, const int64_t* cells, int64_t m,
-                     int want_margin, int nthreads, int mode) {
-    Input in{xyz, w, n, {box[0], box[1], box[2], box[3], box[4], box[5]}, {}, {}};
+Session* open_session(const double* xyz, const double* w, int64_t n, const double* box, int nthreads, int mode) {
 #ifdef _OPENMP
     if (nthreads > 0) omp_set_num_threads(nthreads);
 #endif
+    Session* sp = new Session;
+    Session& S = *sp;
+    S.xyz.assign(xyz, xyz + 3 * n);
+    if (w) S.w.assign(w, w + n);
+    S.in = Input{S.xyz.data(), w ? S.w.data() : nullptr, n, {box[0], box[1], box[2], box[3], box[4], box[5]}, {}, {},
+                 -1};
+    xyz = S.xyz.data();
+    w = w ? S.w.data() : nullptr;
     // coincident sites: sort by position, the heaviest of each run of equal
     // positions (lowest index among equals) is the only one that keeps a cell
-    in.loser.assign((size_t)n, 0);
-    in.twin.assign((size_t)n, 0);
+    S.in.loser.assign((size_t)n, 0);
+    S.in.twin.assign((size_t)n, 0);
     {
         std::vector<int64_t> ord((size_t)n);
         for (int64_t k = 0; k < n; ++k) ord[(size_t)k] = k;
@@ -798,27 +799,32 @@ static void* run_impl(const double* xyz, const double* w, int64_t n, const doubl
                    xyz[3 * ord[b] + 2] == xyz[3 * ord[a] + 2])
                 ++b;
             if (b - a > 1) {
-                for (size_t t = a; t < b; ++t) in.twin[(size_t)ord[t]] = 1;
+                for (size_t t = a; t < b; ++t) S.in.twin[(size_t)ord[t]] = 1;
                 size_t win = a;
                 for (size_t t = a + 1; t < b; ++t) {
                     double wt = w ? (double)w[ord[t]] : 0.0, ww = w ? (double)w[ord[win]] : 0.0;
                     if (wt > ww || (wt == ww && ord[t] < ord[win])) win = t;
                 }
                 for (size_t t = a; t < b; ++t)
-                    if (t != win) in.loser[(size_t)ord[t]] = 1;
+                    if (t != win) S.in.loser[(size_t)ord[t]] = 1;
             }
             a = b;
         }
     }
-    KdTree tree;
-    const bool use_kd = mode == 2 || (mode == 0 && n > 20000);
-    if (use_kd) kd_build(in, tree);
+    S.use_kd = mode == 2 || (mode == 0 && n > 20000);
+    if (S.use_kd) kd_build(S.in, S.tree);
+    return sp;
+}
+
+Result* compute(Session& S, const int64_t* cells, int64_t m, int want_margin) {
+    const Input& in = S.in;
+    const int64_t n = in.n;
     Result* res = new Result;
     const int64_t count = cells ? m : n;
     res->cells.resize((size_t)count);
 #pragma omp parallel
     {
-        Builder B(in, use_kd ? &tree : nullptr);
+        Builder B(in, S.use_kd ? &S.tree : nullptr);
         Poly P;
 #pragma omp for schedule(dynamic, 4)
         for (int64_t t = 0; t < count; ++t) {
@@ -857,6 +863,77 @@ static void* run_impl(const double* xyz, const double* w, int64_t n, const doubl
     }
     return res;
 }
+
+}  // namespace
+
+extern "C" {
+
+// Compute cells `cells[0..m)` (all n cells if cells == NULL).  `box` is
+// [lo.xyz, hi.xyz] in FP64.  Returns an opaque handle, or NULL on bad input.
+// `want_margin` = 0 skips the robustness margin (faster).  `mode`: candidate
+// enumeration, 1 brute force, 2 k-d tree, 0 brute force up to 20000 sites and
+// the k-d tree above (the results are identical).
+void* orc_run(const float* xyz, const float* w, int64_t n, const double* box, const int64_t* cells, int64_t m,
+              int want_margin, int nthreads, int mode) {
+    if (n <= 0 || !xyz || !box || mode < 0 || mode > 2) return nullptr;
+    std::vector<double> x((size_t)(3 * n)), ww;
+    for (int64_t k = 0; k < 3 * n; ++k) x[(size_t)k] = (double)xyz[k];
+    if (w) {
+        ww.resize((size_t)n);
+        for (int64_t k = 0; k < n; ++k) ww[(size_t)k] = (double)w[k];
+    }
+    Session* S = open_session(x.data(), w ? ww.data() : nullptr, n, box, nthreads, mode);
+    Result* r = compute(*S, cells, m, want_margin);
+    delete S;
+    return r;
+}
+
+// The same with FP64 sites and weights.
+void* orc_run64(const double* xyz, const double* w, int64_t n, const double* box, const int64_t* cells, int64_t m,
+                int want_margin, int nthreads, int mode) {
+    if (n <= 0 || !xyz || !box || mode < 0 || mode > 2) return nullptr;
+    Session* S = open_session(xyz, w, n, box, nthreads, mode);
+    Result* r = compute(*S, cells, m, want_margin);
+    delete S;
+    return r;
+}
+
+// A session keeps FP64 sites (and the k-d tree) for many calls, each of which
+// may move one site first (finite differences): orc_session_cells computes
+// the cells `cells[0..m)` with site `moved` (or none, if negative) at
+// moved_xyzw[0..2] with weight moved_xyzw[3], and puts it back afterwards.
+// The moved site must not coincide with another site.  Not thread-safe.
+void* orc_session_open(const double* xyz, const double* w, int64_t n, const double* box, int nthreads, int mode) {
+    if (n <= 0 || !xyz || !box || mode < 0 || mode > 2) return nullptr;
+    return open_session(xyz, w, n, box, nthreads, mode);
+}
+
+void* orc_session_cells(void* h, const int64_t* cells, int64_t m, int want_margin, int64_t moved,
+                        const double* moved_xyzw) {
+    Session& S = *(Session*)h;
+    if (moved >= S.in.n || (moved >= 0 && (!moved_xyzw || S.in.twin[(size_t)moved]))) return nullptr;
+    double keep[4] = {0, 0, 0, 0};
+    if (moved >= 0) {
+        for (int k = 0; k < 3; ++k) {
+            keep[k] = S.xyz[(size_t)(3 * moved + k)];
+            S.xyz[(size_t)(3 * moved + k)] = moved_xyzw[k];
+        }
+        if (!S.w.empty()) {
+            keep[3] = S.w[(size_t)moved];
+            S.w[(size_t)moved] = moved_xyzw[3];
+        }
+        S.in.moved = moved;
+    }
+    Result* r = compute(S, cells, m, want_margin);
+    if (moved >= 0) {
+        for (int k = 0; k < 3; ++k) S.xyz[(size_t)(3 * moved + k)] = keep[k];
+        if (!S.w.empty()) S.w[(size_t)moved] = keep[3];
+        S.in.moved = -1;
+    }
+    return r;
+}
+
+void orc_session_close(void* h) { delete (Session*)h; }
 
 // Totals: [neighbours, vertices, facets, facet-vertices].
 void orc_sizes(const void* h, int64_t* tot) {

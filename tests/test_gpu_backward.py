@@ -297,3 +297,131 @@ def test_vertex_gradient_must_cover_every_vertex():
     short = torch.zeros((d.sizes["n_vert"] - 1, 3), dtype=torch.float32, device="cuda")
     with pytest.raises(ValueError):
         ctx.backward(None, None, short)
+
+
+def _config5_gradient():
+    """The differentiable power diagram of the 1M-site clustered power
+    workload and the gradient of L = sum_i (V_i - |B|/n)^2 + |c_i - p_i|^2
+    through torch autograd (vd_backward), as bench.py times it."""
+    import torch
+    import paper_2605_06408_amd as vd
+    xyz, w, box = wl.make("power_clustered_1m", 0)
+    n = len(xyz)
+    x = torch.from_numpy(xyz).cuda().requires_grad_(True)
+    ww = torch.from_numpy(w).cuda().requires_grad_(True)
+    ctx = vd.Context(0)
+    d = vd.power_diagram(x, ww, bbox=[float(v) for v in box], context=ctx)
+    loss = ((d.vol - 1.0 / n) ** 2).sum() + ((d.centroid - x) ** 2).sum()
+    loss.backward()
+    torch.cuda.synchronize()
+    return xyz, w, box, d, x.grad.cpu().numpy(), ww.grad.cpu().numpy()
+
+
+def test_config5_finite_differences(oracle_mod):
+    """FP64 central finite differences of the config-5 loss on 1000 sampled
+    sites (500 uniformly, 500 among non-empty cells: about 92% of the cells
+    are empty), through the oracle with the site moved (steps 1e-6 l and
+    1e-6 l^2 for positions and weights, l the cell's diagonal or, for an empty
+    cell, the nearest-site distance), against vd_backward.  A site is compared
+    where its cell and its neighbours' cells are certified (the combinatorics
+    hold under the step) and match the GPU's."""
+    import oracle
+    xyz, w, box, d, gp, gw = _config5_gradient()
+    n = len(xyz)
+    rng = np.random.default_rng(1000)
+    flags = d.flags.cpu().numpy()
+    nonempty = np.nonzero((flags & 1) == 0)[0]
+    sites = np.unique(np.concatenate([rng.choice(n, 500, replace=False), rng.choice(nonempty, 500, replace=False)]))
+    first = oracle.cells(xyz, w, box, ids=sites)
+    need = np.unique(np.concatenate([sites, first["nbr"]]))
+    res = oracle.cells(xyz, w, box, ids=need)
+    row = {int(i): t for t, i in enumerate(need)}
+    ok = _same_topology_sites(d, res, sites)
+    cert = [int(k) for k in ok
+            if all(res["margin"][row[int(j)]] >= 1e-5
+                   for j in np.concatenate([[k], res["nbr"][res["nbr_off"][row[int(k)]]:res["nbr_off"][row[int(k)] + 1]]]))]
+    assert len(cert) >= 0.8 * len(sites), (len(cert), len(sites))
+    x64, w64 = xyz.astype(np.float64), w.astype(np.float64)
+    S = oracle.Session(x64, w64, box)
+
+    def local_loss(k, cells, pk, wk):
+        r = S.cells(cells, moved=(k, pk, wk))
+        p = x64[cells].copy()
+        p[cells == k] = pk
+        return float(np.sum((r["vol"] - 1.0 / n) ** 2) + np.sum((r["centroid"] - p) ** 2))
+
+    fd_p = np.zeros((n, 3))
+    fd_w = np.zeros(n)
+    for k in cert:
+        t = row[k]
+        cells = np.unique(np.concatenate([[k], res["nbr"][res["nbr_off"][t]:res["nbr_off"][t + 1]]]))
+        v = res["vert"][res["vert_off"][t]:res["vert_off"][t + 1]]
+        ell = float(np.linalg.norm(v.max(0) - v.min(0))) if len(v) else float(
+            np.sort(np.linalg.norm(x64 - x64[k], axis=1))[1])
+        hp, hw = 1e-6 * ell, 1e-6 * ell * ell
+        for c in range(3):
+            e = np.zeros(3)
+            e[c] = hp
+            fd_p[k, c] = (local_loss(k, cells, x64[k] + e, w64[k]) - local_loss(k, cells, x64[k] - e, w64[k])) / (2 * hp)
+        fd_w[k] = (local_loss(k, cells, x64[k], w64[k] + hw) - local_loss(k, cells, x64[k], w64[k] - hw)) / (2 * hw)
+    S.close()
+    cert = np.array(cert, np.int64)
+    ep = _compare(gp, fd_p, cert)
+    ew = _compare(gw, fd_w, cert)
+    print("config 5 finite differences: %d of %d sites, max rel err positions %.2e weights %.2e"
+          % (len(cert), len(sites), ep.max(), ew.max()))
+    assert ep.max() <= GRAD_TOL and ew.max() <= GRAD_TOL
+
+
+def test_config5_volume_weight_closed_form():
+    """dV_i/dw_j = -A_ij / (2 D_ij) for a neighbour j and
+    dV_i/dw_i = sum_j A_ij / (2 D_ij) (box facets do not depend on weights),
+    with A_ij the area of the GPU's own facet ring (FP64 shoelace) and
+    D_ij = |p_j - p_i|: vd_backward with g_vol = 1 on 300 non-empty cells of
+    the 1M-site clustered power workload that share no neighbour."""
+    import torch
+    import paper_2605_06408_amd as vd
+    from .parity import to_numpy
+    xyz, w, box = wl.make("power_clustered_1m", 0)
+    n = len(xyz)
+    ctx = vd.Context(0)
+    d = ctx.build(torch.from_numpy(xyz).cuda(), torch.from_numpy(w).cuda(), bbox=[float(v) for v in box])
+    flags = d.flags.cpu().numpy()
+    off = d.nbr_off.cpu().numpy()
+    nbr = d.nbr.cpu().numpy()
+    rng = np.random.default_rng(5)
+    chosen, taken = [], set()
+    for i in rng.permutation(np.nonzero((flags & 1) == 0)[0]):
+        nb = set(nbr[off[i]:off[i + 1]].tolist()) | {int(i)}
+        if nb & taken:
+            continue
+        chosen.append(int(i))
+        taken |= nb
+        # the neighbours' other neighbours may be chosen; their g_w then mixes
+        # two cells, so every site next to a chosen cell is reserved
+        if len(chosen) == 300:
+            break
+    g_vol = np.zeros(n, np.float32)
+    g_vol[chosen] = 1.0
+    _, g_w = ctx.backward(torch.from_numpy(g_vol).cuda(), None, None)
+    g_w = g_w.cpu().numpy().astype(np.float64)
+    g = to_numpy(d, np.array(chosen))
+    worst = 0.0
+    for t, i in enumerate(chosen):
+        own, err = 0.0, 0.0
+        for f in range(g["facet_off"][t], g["facet_off"][t + 1]):
+            j = int(g["facet_nbr"][f])
+            if j < 0:
+                continue
+            ring = g["vert"][g["fv"][g["fv_off"][f]:g["fv_off"][f + 1]]].astype(np.float64)
+            ring = ring - ring[0]
+            area = 0.5 * np.linalg.norm(sum(np.cross(ring[q], ring[(q + 1) % len(ring)]) for q in range(len(ring))))
+            D = float(np.linalg.norm(xyz[j].astype(np.float64) - xyz[i].astype(np.float64)))
+            own += area / (2 * D)
+            # i is the only chosen cell next to j
+            err = max(err, abs(g_w[j] + area / (2 * D)))
+        err = max(err, abs(g_w[i] - own))
+        worst = max(worst, err / own)
+    print("closed form dV/dw on %d cells: max error %.2e of sum_j A_ij / (2 D_ij)" % (len(chosen), worst))
+    assert len(chosen) == 300
+    assert worst <= 1e-4

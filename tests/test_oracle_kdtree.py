@@ -63,3 +63,31 @@ def test_kdtree_mode_on_sampled_cells():
     b = oracle.cells(xyz, w, box, ids=ids, candidates="kdtree")
     for k in KEYS:
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_session_with_a_moved_site_matches_a_fresh_run():
+    """oracle.Session keeps the sites and the k-d tree across calls and can
+    move one site first (finite differences): its cells equal those of a
+    brute-force run on a copy with that site moved."""
+    xyz, w, box = wl.make("power_clustered_1m", 0, 60000)
+    x64, w64 = xyz.astype(np.float64), w.astype(np.float64)
+    S = oracle.Session(x64, w64, box, candidates="kdtree")
+    rng = np.random.default_rng(0)
+    nonempty = np.nonzero((oracle.cells(xyz, w, box, ids=np.arange(0, 60000, 7), margin=False)["flags"] & 1) == 0)[0] * 7
+    for k in list(rng.choice(60000, 10, replace=False)) + list(rng.choice(nonempty, 10, replace=False)):
+        k = int(k)
+        pk = x64[k] + rng.normal(size=3) * 1e-4
+        wk = w64[k] * (1.0 + 1e-3)
+        nb = oracle.cells(x64, w64, box, ids=[k], fp64=True)["nbr"]
+        ids = np.unique(np.concatenate([[k], nb, rng.choice(60000, 5)]))
+        a = S.cells(ids, margin=True, moved=(k, pk, wk))
+        x2, w2 = x64.copy(), w64.copy()
+        x2[k], w2[k] = pk, wk
+        b = oracle.cells(x2, w2, box, ids=ids, fp64=True, candidates="brute")
+        for q in KEYS:
+            assert np.array_equal(a[q], b[q]), (k, q)
+        # and the site is back in place afterwards
+        c = S.cells(ids, margin=True)
+        d = oracle.cells(x64, w64, box, ids=ids, fp64=True, candidates="brute")
+        for q in KEYS:
+            assert np.array_equal(c[q], d[q]), (k, q)
