@@ -58,7 +58,10 @@ typedef struct vd_options {
     int32_t culling;    /* 1 = directional (Sec. 4.2.1-4.2.2), 2 = isotropic radius,
                            3 = directional plus vertex power-ball node test and
                                exact plane-versus-cell-box site test (default) */
-    int32_t traversal;  /* 1 = best-first (Alg. 1, default), 2 = depth-first */
+    int32_t traversal;  /* 1 = best-first (Alg. 1, default): the queued node of least
+                           bound next; 2 = depth-first (ablation): the node queued
+                           last next.  Both descend into the nearer child first and
+                           clip a leaf's sites nearest plane first */
     int32_t profile;    /* 1 = record per-phase HIP-event timings (vd_get_timings) */
     int32_t counters;   /* 1 = count the method's work units (vd_get_counters) */
     int32_t reserved[2];
@@ -218,6 +221,27 @@ VD_API vd_status vd_backward(vd_context* ctx, const float* g_vol, const float* g
  * written), VD_ERR_STATE without a build. */
 VD_API vd_status vd_tetrahedra(vd_context* ctx, int32_t* tets, int64_t capacity, int64_t* count, void* stream);
 
+/* The bounding-volume hierarchy of the last build, for inspection and tests
+ * (Sec. 4.3: a binary BVH over the sites whose nodes also hold the largest
+ * weight below them).  Every output is optional (NULL skips it); device
+ * arrays, written on `stream` (not synchronised):
+ *   morton      uint64[n]  Morton code of each site, caller's order (63 bits,
+ *                          21 per axis inside the build's box)
+ *   sorted_keys uint64[n]  the codes sorted ascending (the radix sort's output)
+ *   order       uint32[n]  Morton position -> caller's index of the site
+ *   nodes       (n-1) records of 64 bytes: for each internal node its two
+ *               children, each { float lo[3]; float wmax; float hi[3];
+ *               uint32 ref }; ref bit 31 set: a leaf of sites at Morton
+ *               positions [ref & 0x1FFFFFF, + ((ref >> 25) & 63) + 1),
+ *               otherwise the index of an internal node
+ *   leaf_of     uint32[n]  per Morton position: (node << 1) | child, the
+ *               record of the leaf that holds the site
+ *   root        HOST uint32: the root reference (a leaf when n <= leaf size;
+ *               nodes and leaf_of are then not written)
+ * VD_ERR_STATE without a build. */
+VD_API vd_status vd_inspect_bvh(vd_context* ctx, uint64_t* morton, uint64_t* sorted_keys, uint32_t* order,
+                                void* nodes, uint32_t* leaf_of, uint32_t* root, void* stream);
+
 /* Counters of the last build (see vd_sizes); host call, no device work. */
 VD_API vd_status vd_get_sizes(const vd_context* ctx, vd_sizes* sizes);
 
@@ -229,6 +253,15 @@ VD_API vd_status vd_get_timings(vd_context* ctx, float* ms, int32_t count);
 /* Work counters of the last build (up to VD_TIERS * VD_CTR_COUNT entries, see
  * VD_CTR_*); needs vd_options.counters = 1. */
 VD_API vd_status vd_get_counters(const vd_context* ctx, uint64_t* out, int32_t count);
+
+/* Achievable peaks of HIP device `device`, for roofline reports: the HBM
+ * bandwidth of a plain float4 stream copy of 1 GiB (bytes read plus written
+ * per second, in GB/s) and the rate of independent FP32 fused multiply-adds
+ * (lane operations per second, one per FMA, in units of 10^12), each the best
+ * of five timed runs (HIP events on `stream`) after one warm-up run.
+ * Allocates and frees 2 GiB of device scratch; host-blocking.  Not part of
+ * building a diagram. */
+VD_API vd_status vd_measure_peaks(int device, void* stream, double* copy_gbs, double* fma_tops);
 
 /* Message for the last error on this thread ("" if none). */
 VD_API const char* vd_last_error(void);

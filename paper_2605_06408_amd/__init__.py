@@ -112,6 +112,11 @@ def load_library():
             lib.vd_get_counters.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32]
             lib.vd_backward.restype = ctypes.c_int
             lib.vd_backward.argtypes = [P, P, P, P, P, P, P]
+            lib.vd_inspect_bvh.restype = ctypes.c_int
+            lib.vd_inspect_bvh.argtypes = [P, P, P, P, P, P, ctypes.POINTER(ctypes.c_uint32), P]
+            lib.vd_measure_peaks.restype = ctypes.c_int
+            lib.vd_measure_peaks.argtypes = [ctypes.c_int, P, ctypes.POINTER(ctypes.c_double),
+                                             ctypes.POINTER(ctypes.c_double)]
             lib.vd_tetrahedra.restype = ctypes.c_int
             lib.vd_tetrahedra.argtypes = [P, P, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), P]
             _lib = lib
@@ -249,6 +254,30 @@ class Context:
                                           ctypes.c_void_p(stream)), "vd_tetrahedra")
         return tets
 
+    def inspect_bvh(self) -> dict:
+        """vd_inspect_bvh over the last build: Morton codes (caller's order),
+        sorted codes, Morton order, node records [n-1, 2] of
+        (lo xyz, wmax, hi xyz, ref) as int32/float32 views, leaf records and
+        the root reference."""
+        import torch
+        dev = self.device
+        n = self.n
+        t = dict(morton=torch.empty(n, dtype=torch.int64, device=dev),
+                 sorted_keys=torch.empty(n, dtype=torch.int64, device=dev),
+                 order=torch.empty(n, dtype=torch.int32, device=dev),
+                 nodes=torch.zeros((max(n - 1, 1), 2, 8), dtype=torch.int32, device=dev),
+                 leaf_of=torch.zeros(n, dtype=torch.int32, device=dev))
+        root = ctypes.c_uint32(0)
+        stream = torch.cuda.current_stream(dev).cuda_stream
+        with torch.cuda.device(dev):
+            _check(self.lib.vd_inspect_bvh(self.handle, _ptr(t["morton"]), _ptr(t["sorted_keys"]), _ptr(t["order"]),
+                                           _ptr(t["nodes"]), _ptr(t["leaf_of"]), ctypes.byref(root),
+                                           ctypes.c_void_p(stream)), "vd_inspect_bvh")
+        torch.cuda.synchronize(dev)
+        out = {k: v.cpu().numpy() for k, v in t.items()}
+        out["root"] = root.value
+        return out
+
     def backward(self, g_vol=None, g_cen=None, g_vert=None, want_w=True):
         """vd_backward over the last build: gradients of
         sum g_vol V + g_cen . c + g_vert . x with respect to the sites (and
@@ -330,6 +359,20 @@ def power_diagram(xyz, w=None, bbox=None, context: Context | None = None, **opti
     d = dict(zip(OUTPUT_FIELDS, outs))
     d["sizes"] = ctx.last_sizes
     return Diagram(**d)
+
+
+def measure_peaks(device=None) -> dict:
+    """vd_measure_peaks: achievable HBM copy bandwidth (GB/s) and FP32 FMA
+    rate (10^12 lane operations per second) of the device."""
+    import torch
+    dev = torch.device("cuda", torch.cuda.current_device() if device is None else torch.device(device).index or 0)
+    lib = load_library()
+    cg, ft = ctypes.c_double(0.0), ctypes.c_double(0.0)
+    stream = torch.cuda.current_stream(dev).cuda_stream
+    with torch.cuda.device(dev):
+        _check(lib.vd_measure_peaks(dev.index, ctypes.c_void_p(stream), ctypes.byref(cg), ctypes.byref(ft)),
+               "vd_measure_peaks")
+    return {"copy_GBs": cg.value, "fma_Tops": ft.value}
 
 
 _contexts: dict = {}

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libvd.so")
 BUILD = os.path.join(HERE, "_build")
-SOURCES = ["vd_api.hip", "vd_lbvh.hip", "vd_csr.hip", "vd_clip.hip", "vd_bwd.hip"]
+SOURCES = ["vd_api.hip", "vd_lbvh.hip", "vd_csr.hip", "vd_clip.hip", "vd_bwd.hip", "vd_peaks.hip"]
 
 
 def hipcc() -> str:

@@ -11,6 +11,7 @@ namespace {
 
 thread_local std::string g_err;
 
+
 vd_status fail(vd_status s, const std::string& msg) {
     g_err = msg;
     return s;
@@ -33,6 +34,7 @@ struct vd_context {
     int device = 0;
     int num_cu = 0;
     // grow-only device scratch
+    // pint: parent links of the internal nodes; pleaf: leaf record of each site
     DevBuf pts, spts, keys[2], vals[2], inv, mark, child, pint, pleaf, range, counters, nodes, hist, stmp, bbox,
         bpart, misc, loc, cnt_v, cnt_f, cnt_n, vol, cen, flags, offv, offf, offn, scan_tmp, stats, ctr;
     DevBuf lists[vd::kTiers];  // lists[t]: cells handed on to tier t (t >= 1)
@@ -41,11 +43,15 @@ struct vd_context {
     DevBuf handoff;  // cells the 1024-vertex pass hands to the last one
     DevBuf tet_cnt, tet_off;  // dual tetrahedra per cell and their offsets
     DevBuf bwd_facet, bwd_self, bwd_orphan, bwd_box;  // backward scratch
+    DevBuf inspect;  // scratch of vd_inspect_bvh
     // last build
     bool valid = false;
     int64_t n = 0;
     vd_sizes sizes{};
     const uint32_t* order = nullptr;
+    const uint64_t* skeys = nullptr;  // sorted Morton codes of the last build
+    uint32_t root = 0;
+    int leaf_size = 0;
     int tier_slots[vd::kTiers] = {};
     // profiling: events e[0..6] bracket the build phases, e[7..8] the write,
     // e[9..10] the backward
@@ -160,7 +166,7 @@ VD_API void vd_destroy(vd_context* c) {
                      &c->bbox, &c->bpart, &c->misc, &c->loc, &c->cnt_v, &c->cnt_f, &c->cnt_n, &c->vol, &c->cen,
                      &c->flags, &c->offv, &c->offf, &c->offn, &c->scan_tmp, &c->stats,
                      &c->ctr, &c->arena, &c->handoff, &c->tet_cnt, &c->tet_off, &c->bwd_facet, &c->bwd_self,
-                     &c->bwd_orphan, &c->bwd_box};
+                     &c->bwd_orphan, &c->bwd_box, &c->inspect};
     for (DevBuf* b : all) release(*b);
     if (c->ev_ready)
         for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
@@ -279,10 +285,9 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     VD_HIP(vd::launch_losers(spts, skeys, order, n, as<uint8_t>(c->mark), s));
     uint32_t root;
     if (n > o.leaf_size) {
-        VD_HIP(vd::launch_karras(skeys, n, as<int2>(c->child), as<int>(c->pint), as<int>(c->pleaf),
-                                 as<int2>(c->range), s));
+        VD_HIP(vd::launch_karras(skeys, n, as<int2>(c->child), as<uint32_t>(c->pint), as<int2>(c->range), s));
         VD_HIP(vd::launch_bounds(spts, n, as<int2>(c->child), as<int2>(c->range), as<vd::NodeChild>(c->counters),
-                                 as<vd::Node>(c->nodes), o.leaf_size, s));
+                                 as<vd::Node>(c->nodes), as<uint32_t>(c->pleaf), o.leaf_size, s));
         root = 0;
     } else {
         root = vd::leaf_ref(0u, (uint32_t)n);
@@ -293,6 +298,8 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     a.order = order;
     a.nodes = as<vd::Node>(c->nodes);
     a.root = root;
+    a.up = as<uint32_t>(c->pint);
+    a.leaf_of = vd::ref_is_leaf(root) ? nullptr : as<uint32_t>(c->pleaf);
     a.bbox = dbbox;
     a.n = n;
     a.leaf_size = o.leaf_size;
@@ -401,6 +408,9 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     c->sizes = z;
     c->n = n;
     c->order = order;
+    c->skeys = skeys;
+    c->root = root;
+    c->leaf_size = o.leaf_size;
     c->box_given = bbox != nullptr;
     c->valid = true;
     *sizes = z;
@@ -481,6 +491,31 @@ VD_API vd_status vd_tetrahedra(vd_context* c, int32_t* tets, int64_t capacity, i
     if (capacity < total) return fail(VD_ERR_INVALID_ARG, "vd_tetrahedra: capacity below the count");
     a.tets = tets;
     if (total > 0) VD_HIP(vd::launch_tet_write(a, s));
+    return VD_OK;
+}
+
+VD_API vd_status vd_inspect_bvh(vd_context* c, uint64_t* morton, uint64_t* sorted_keys, uint32_t* order,
+                                void* nodes, uint32_t* leaf_of, uint32_t* root, void* stream) {
+    g_err.clear();
+    if (!c || !root) return fail(VD_ERR_INVALID_ARG, "vd_inspect_bvh: null argument");
+    if (!c->valid) return fail(VD_ERR_STATE, "vd_inspect_bvh: no successful build");
+    VD_HIP(hipSetDevice(c->device));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = c->n;
+    *root = c->root;
+    if (morton) {
+        // codes of the sites in the caller's order, recomputed as the build made them
+        VD_TRY(ensure(c->inspect, (size_t)n * sizeof(uint32_t)));
+        VD_HIP(vd::launch_morton(as<float4>(c->pts), n, as<float>(c->bbox), morton, as<uint32_t>(c->inspect), s));
+    }
+    if (sorted_keys)
+        VD_HIP(hipMemcpyAsync(sorted_keys, c->skeys, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    if (order) VD_HIP(hipMemcpyAsync(order, c->order, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
+    const bool tree = !vd::ref_is_leaf(c->root);
+    if (nodes && tree)
+        VD_HIP(hipMemcpyAsync(nodes, c->nodes.p, (size_t)(n - 1) * sizeof(vd::Node), hipMemcpyDeviceToDevice, s));
+    if (leaf_of && tree)
+        VD_HIP(hipMemcpyAsync(leaf_of, c->pleaf.p, (size_t)n * sizeof(uint32_t), hipMemcpyDeviceToDevice, s));
     return VD_OK;
 }
 

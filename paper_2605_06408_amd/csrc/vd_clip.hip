@@ -1379,10 +1379,9 @@ struct Cell {
             if (mask && robust < 2) mask = cutting(mask, ax, ay, az, b, 0.5f * (a2 + fabsf(dw)));
         }
         while (mask) {
+            // nearest plane first (both traversal orders)
             int L;
-            if (A.traversal == 2) {
-                L = lowest(mask);
-            } else {
+            {
                 float kk = ((mask >> ln) & 1) ? key : INFINITY;
                 float m = wmin(kk);
                 uint64_t mm = ballot(kk == m) & mask;
@@ -1418,6 +1417,61 @@ struct Cell {
         c->hi[0] = v.x; c->hi[1] = v.y; c->hi[2] = v.z; c->ref = __float_as_uint(v.w);
     }
 
+    // The start of Alg. 1.  From the root, the walk first reaches the site's
+    // own leaf (its bound is 0 there) and on the way down queues the sibling
+    // of every node on that path, tested against the still uncut box.  Here
+    // the own leaf (found through the site's leaf record) is clipped first;
+    // then the siblings of its path are gathered by one scalar climb over the
+    // parent links, one per lane, and tested together against the cut cell.
+    // Only those that may still cut it are queued, with the keys Alg. 1 gives
+    // them (a sibling culled here would be culled when popped: the cell only
+    // shrinks), top of the path first so that the nearest is queued last.
+    // Returns kNone, or what the leaf returned (kEmptied, kOverflow,
+    // kRestart); *deep if the path has more than 64 siblings (the walk then
+    // starts at the root and passes over the own leaf).
+    __device__ int own_leaf_start(uint32_t* own, bool* deep) {
+        KArgs* ka = cold_args();
+        const uint32_t rec = uni(ka->leaf_of[self]);
+        const uint32_t oref = uni(A.nodes[rec >> 1].c[rec & 1].ref);
+        *own = oref;
+        *deep = false;
+        const uint64_t t0 = tic();
+        int r = leaf(oref, ~0ull);
+        toc(kCtrCycLeaf, t0);
+        if constexpr (CAP == kHandoffCap) ov_ok = false;  // no queue yet: a later pass starts over
+        if (r != kNone) return r;
+        uint32_t e = rec ^ 1u;  // this lane's sibling record: (node << 1) | which child
+        int ns = 1;
+        for (uint32_t cur = rec;;) {
+            const uint32_t u = uni(ka->up[cur >> 1]);
+            if (u == kNoParent) break;
+            if (ns == 64) {
+                *deep = true;
+                return kNone;
+            }
+            if ((int)ln == ns) e = u ^ 1u;
+            ++ns;
+            cur = u;
+        }
+        count(kCtrNode, (uint64_t)ns);
+        // lanes past the path test the first sibling again (no divergent load)
+        const uint32_t me = (int)ln < ns ? e : rdl(e, 0);
+        NodeChild c;
+        load_child(me >> 1, (int)(me & 1), &c);
+        float key = 0.f, delta = 0.f;
+        bool cull = true;
+        node_test(c, &key, &cull, &delta);
+        uint64_t live = ballot(!cull && (int)ln < ns);
+        while (live) {
+            const int L = 63 - __builtin_clzll(live);
+            live &= ~(1ull << L);
+            if (A.culling == 3 && !ball_hit_lane(c, L)) continue;
+            if (qn >= CAP) return kOverflow;
+            push(rdl(me, L), rdl(key, L));
+        }
+        return kNone;
+    }
+
     // Alg. 1.  Returns kNone when done, kEmptied, kOverflow or kRestart.
     // A cell taken over from the previous pass (resume) first finishes the
     // leaf it stopped in, then goes on with the queue it brought.
@@ -1432,6 +1486,16 @@ struct Cell {
             }
         }
         if constexpr (CAP == kHandoffCap) ov_ok = false;
+        // own leaf first, then the siblings of its path (not for a cell taken over)
+        uint32_t done_leaf = 0;
+        bool skip_done = false;
+        if (!resume && A.leaf_of != nullptr) {
+            bool deep;
+            const int r = own_leaf_start(&done_leaf, &deep);
+            if (r != kNone) return r;
+            have = deep;
+            skip_done = deep;
+        }
         // every node is visited at most once in a valid tree; the bound only
         // guarantees termination if the tree were ever malformed
         int64_t budget = 4 * A.n + 1024;
@@ -1464,10 +1528,12 @@ struct Cell {
                     have = false;
                     break;
                 }
+                // descend into the nearer child (smaller bound minus radius),
+                // queue the other: the same in both traversal orders, which
+                // differ only in what they pop next (Alg. 1: the least key;
+                // depth-first: the last pushed)
                 const float d0 = rdl(delta, 0), d1 = rdl(delta, 1);
-                int near;
-                if (A.traversal == 2) near = c0 ? 1 : 0;
-                else near = c1 ? 0 : (c0 ? 1 : (d0 <= d1 ? 0 : 1));
+                const int near = c1 ? 0 : (c0 ? 1 : (d0 <= d1 ? 0 : 1));
                 const int far = 1 - near;
                 if (!(far ? c1 : c0)) {
                     if (qn >= CAP) return kOverflow;
@@ -1475,7 +1541,7 @@ struct Cell {
                 }
                 cur = rdl(ref, near);
             }
-            if (have) {
+            if (have && !(skip_done && cur == done_leaf)) {
                 const uint64_t t0 = tic();
                 int r = leaf(cur, allow);
                 if constexpr (CAP > kHandoffCap) allow = ~0ull;

@@ -39,6 +39,7 @@ struct __align__(16) Node {
 };
 
 constexpr uint32_t kLeafBit = 0x80000000u;
+constexpr uint32_t kNoParent = 0xFFFFFFFFu;  // parent link of the root
 __host__ __device__ inline uint32_t leaf_ref(uint32_t first, uint32_t count) {
     return kLeafBit | ((count - 1u) << 25) | first;
 }
@@ -105,6 +106,9 @@ struct ClipArgs {
     const uint32_t* order;    // Morton position -> original index
     const Node* nodes;        // internal nodes (n-1)
     uint32_t root;            // root reference
+    const uint32_t* up;       // [n-1] parent link of each internal node: (parent << 1) | which child
+    const uint32_t* leaf_of;  // [n] by Morton position: (node << 1) | which child holds the site's leaf
+                              // (null when the root is a leaf)
     const float* bbox;        // device [6]: lo.xyz, hi.xyz
     int64_t n;
     int leaf_size;
@@ -212,13 +216,16 @@ hipError_t launch_gather(const float4* pts, const uint32_t* order, int64_t n, fl
                          hipStream_t s);
 hipError_t launch_losers(float4* spts, const uint64_t* keys, const uint32_t* order, int64_t n, uint8_t* mark,
                          hipStream_t s);
-hipError_t launch_karras(const uint64_t* keys, int64_t n, int2* child, int* parent_int, int* parent_leaf, int2* range,
-                         hipStream_t s);
+// Binary radix tree over the sorted codes: children, ranges, and the parent
+// link of every internal node ((parent << 1) | which child; kNoParent at the
+// root).
+hipError_t launch_karras(const uint64_t* keys, int64_t n, int2* child, uint32_t* up, int2* range, hipStream_t s);
 // Child boxes and max weights of every internal node (range reductions over a
-// sparse table of 64-site block boxes; table: box_table_size(n) entries).
+// sparse table of 64-site block boxes; table: box_table_size(n) entries), and
+// the leaf record of every site ((node << 1) | which child, by Morton position).
 size_t box_table_size(int64_t n);
 hipError_t launch_bounds(const float4* spts, int64_t n, const int2* child, const int2* range, NodeChild* table,
-                         Node* nodes, int leaf_size, hipStream_t s);
+                         Node* nodes, uint32_t* leaf_of, int leaf_size, hipStream_t s);
 
 // Exclusive scan of uint32 counts into int64 offsets [n+1] (out[n] = total).
 size_t scan_tmp_size(int64_t n);

@@ -291,8 +291,8 @@ __device__ inline int kdelta(const uint64_t* keys, int n, int i, int j) {
     return a != b ? __clzll((long long)(a ^ b)) : 64 + __clz(i ^ j);
 }
 
-__global__ void k_karras(const uint64_t* __restrict__ keys, int n, int2* __restrict__ child, int* __restrict__ parent_int,
-                         int* __restrict__ parent_leaf, int2* __restrict__ range) {
+__global__ void k_karras(const uint64_t* __restrict__ keys, int n, int2* __restrict__ child, uint32_t* __restrict__ up,
+                         int2* __restrict__ range) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
     int d = (kdelta(keys, n, i, i + 1) - kdelta(keys, n, i, i - 1)) >= 0 ? 1 : -1;
@@ -315,16 +315,16 @@ __global__ void k_karras(const uint64_t* __restrict__ keys, int n, int2* __restr
     int right = (last == gamma + 1) ? ~(gamma + 1) : gamma + 1;
     child[i] = make_int2(left, right);
     range[i] = make_int2(first, last);
-    if (left >= 0) parent_int[left] = i; else parent_leaf[~left] = i;
-    if (right >= 0) parent_int[right] = i; else parent_leaf[~right] = i;
-    if (i == 0) parent_int[0] = -1;
+    // parent link of each internal child: parent index and which child it is
+    if (left >= 0) up[left] = (uint32_t)i << 1;
+    if (right >= 0) up[right] = ((uint32_t)i << 1) | 1u;
+    if (i == 0) up[0] = kNoParent;
 }
 
-hipError_t launch_karras(const uint64_t* keys, int64_t n, int2* child, int* parent_int, int* parent_leaf, int2* range,
-                         hipStream_t s) {
+hipError_t launch_karras(const uint64_t* keys, int64_t n, int2* child, uint32_t* up, int2* range, hipStream_t s) {
     if (n < 2) return hipSuccess;
-    hipLaunchKernelGGL(k_karras, dim3((unsigned)((n - 1 + 255) / 256)), dim3(256), 0, s, keys, (int)n, child,
-                       parent_int, parent_leaf, range);
+    hipLaunchKernelGGL(k_karras, dim3((unsigned)((n - 1 + 255) / 256)), dim3(256), 0, s, keys, (int)n, child, up,
+                       range);
     return hipGetLastError();
 }
 
@@ -455,6 +455,23 @@ __global__ void k_node_boxes(const float4* __restrict__ spts, int n, const int2*
     }
 }
 
+// The leaf record of every site: the node whose child record is the leaf
+// (a subtree of at most leaf_size sites under a node of more) and which child.
+__global__ void k_leaf_of(const int2* __restrict__ child, const int2* __restrict__ range, int n, int leaf_size,
+                          uint32_t* __restrict__ leaf_of) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    int2 r = range[i];
+    if (r.y - r.x + 1 <= leaf_size) return;
+    int2 ch = child[i];
+    for (int s = 0; s < 2; ++s) {
+        int c = s ? ch.y : ch.x;
+        int f = c < 0 ? ~c : range[c].x, l = c < 0 ? ~c : range[c].y;
+        if (l - f + 1 > leaf_size) continue;
+        for (int k = f; k <= l; ++k) leaf_of[k] = ((uint32_t)i << 1) | (uint32_t)s;
+    }
+}
+
 size_t box_table_size(int64_t n) {
     int64_t nb = (n + 63) / 64;
     int levels = 1;
@@ -463,7 +480,7 @@ size_t box_table_size(int64_t n) {
 }
 
 hipError_t launch_bounds(const float4* spts, int64_t n, const int2* child, const int2* range, NodeChild* table,
-                         Node* nodes, int leaf_size, hipStream_t s) {
+                         Node* nodes, uint32_t* leaf_of, int leaf_size, hipStream_t s) {
     if (n < 2) return hipSuccess;
     const int64_t nb = (n + 63) / 64;
     hipLaunchKernelGGL(k_block_boxes, dim3((unsigned)((nb * 64 + 255) / 256)), dim3(256), 0, s, spts, n, table, nb);
@@ -474,6 +491,8 @@ hipError_t launch_bounds(const float4* spts, int64_t n, const int2* child, const
     }
     hipLaunchKernelGGL(k_node_boxes, dim3((unsigned)((n - 1 + 255) / 256)), dim3(256), 0, s, spts, (int)n, child,
                        range, table, nb, nodes, leaf_size);
+    hipLaunchKernelGGL(k_leaf_of, dim3((unsigned)((n - 1 + 255) / 256)), dim3(256), 0, s, child, range, (int)n,
+                       leaf_size, leaf_of);
     return hipGetLastError();
 }
 
