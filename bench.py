@@ -88,6 +88,7 @@ def parse():
     ap.add_argument("--leaf-size", type=int, default=0)
     ap.add_argument("--culling", type=int, default=3)
     ap.add_argument("--traversal", type=int, default=1)
+    ap.add_argument("--warm-start", type=int, default=0, help="K of the KNN warm start (0: none)")
     ap.add_argument("--weight-ratio", type=float, default=None,
                     help="replace the weights by w ~ N(0, (ratio * d_nn)^2), d_nn the median "
                          "nearest-neighbour distance (the paper's weight sweep)")
@@ -371,7 +372,8 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    kw = dict(precision=args.precision, leaf_size=args.leaf_size, culling=args.culling, traversal=args.traversal)
+    kw = dict(precision=args.precision, leaf_size=args.leaf_size, culling=args.culling, traversal=args.traversal,
+              warm_start=args.warm_start)
     rep, ctx, (tx, tw, bbox) = run_leg(args.config, xyz, w, box, kw, args.steps, args.warmup, "headline", True)
     ms = rep["ms_per_step"]
     k = rep["dominant_kernel"]
@@ -387,7 +389,8 @@ def main():
         "config": {"workload": args.config, "n": n, "seed": args.seed, "box": bbox,
                    "weights": w is not None, "precision": "fp32" if args.precision == 1 else "mixed fp32/fp64",
                    "weight_ratio": args.weight_ratio,
-                   "leaf_size": args.leaf_size or 32, "culling": args.culling, "traversal": args.traversal},
+                   "leaf_size": args.leaf_size or 32, "culling": args.culling, "traversal": args.traversal,
+                   "warm_start": args.warm_start},
         "roofline": roofline,
         "step_roofline": rep["step_roofline"],
         "phases_ms": rep["phases_ms"],

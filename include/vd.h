@@ -64,7 +64,10 @@ typedef struct vd_options {
                            clip a leaf's sites nearest plane first */
     int32_t profile;    /* 1 = record per-phase HIP-event timings (vd_get_timings) */
     int32_t counters;   /* 1 = count the method's work units (vd_get_counters) */
-    int32_t reserved[2];
+    int32_t warm_start; /* K = 1..16: KNN warm start (supplementary Sec. A): each cell is
+                           first clipped by its K nearest sites, found by a best-first
+                           query of the same BVH; 0 = none (default) */
+    int32_t reserved;
 } vd_options;
 
 /* Phases reported by vd_get_timings (milliseconds, HIP events on `stream`). */

@@ -53,7 +53,7 @@ class VDError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("culling", ctypes.c_int32),
                 ("traversal", ctypes.c_int32), ("profile", ctypes.c_int32), ("counters", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("warm_start", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Sizes(ctypes.Structure):
@@ -163,7 +163,7 @@ class Context:
 
     def build_sizes(self, xyz, w=None, bbox=None, precision=PRECISION_FP32, leaf_size=0,
                     culling=CULLING_BALLS, traversal=TRAVERSAL_BEST_FIRST, allow_failed=False,
-                    profile=False, counters=False) -> Sizes:
+                    profile=False, counters=False, warm_start=0) -> Sizes:
         """Run vd_build only (the diagram stays in the context)."""
         import torch
         if not (xyz.is_cuda and xyz.dtype == torch.float32 and xyz.dim() == 2 and xyz.shape[1] == 3):
@@ -180,7 +180,7 @@ class Context:
             if len(vals) != 6:
                 raise ValueError("bbox must have 6 entries")
             hb = (ctypes.c_float * 6)(*vals)
-        opt = Options(precision, leaf_size, culling, traversal, int(profile), int(counters))
+        opt = Options(precision, leaf_size, culling, traversal, int(profile), int(counters), int(warm_start))
         sz = Sizes()
         stream = torch.cuda.current_stream(self.device).cuda_stream
         with torch.cuda.device(self.device):

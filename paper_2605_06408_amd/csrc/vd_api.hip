@@ -206,6 +206,8 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
         return fail(VD_ERR_INVALID_ARG, "vd_build: leaf_size must be in [1, 64]");
     if (o.culling < 1 || o.culling > 3) return fail(VD_ERR_INVALID_ARG, "vd_build: culling must be 1, 2 or 3");
     if (o.traversal < 1 || o.traversal > 2) return fail(VD_ERR_INVALID_ARG, "vd_build: traversal must be 1 or 2");
+    if (o.warm_start < 0 || o.warm_start > vd::kMaxWarm)
+        return fail(VD_ERR_INVALID_ARG, "vd_build: warm_start must be in [0, " + std::to_string(vd::kMaxWarm) + "]");
     if (bbox) {
         for (int k = 0; k < 6; ++k)
             if (!std::isfinite(bbox[k])) return fail(VD_ERR_INVALID_ARG, "vd_build: non-finite bbox");
@@ -305,6 +307,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     a.leaf_size = o.leaf_size;
     a.culling = o.culling;
     a.traversal = o.traversal;
+    a.warm_start = o.warm_start;
     a.precision = o.precision;
     a.loc = as<uint32_t>(c->loc);
     a.cnt_v = as<uint32_t>(c->cnt_v);

@@ -294,6 +294,10 @@ struct Cell {
     Lane<uint32_t> qe;
     Lane<float> qk;
     int qn;
+    // KNN warm start: the sites already clipped (Morton positions), lane t
+    // holding the t-th; the leaves of the walk pass over them
+    int nwarm;
+    uint32_t wsite;
     // where the last capacity overflow struck: in leaf ov_leaf, with the
     // candidates ov_mask still to try (ov_ok), else somewhere not resumable
     bool ov_ok;
@@ -438,6 +442,7 @@ struct Cell {
         px = s.x; py = s.y; pz = s.z; pw = s.w;
         flags = 0;
         qn = 0;
+        nwarm = 0;
         if (pw == -INFINITY) return false;  // coincident with a heavier site
         const float lo[3] = {A.bbox[0] - px, A.bbox[1] - py, A.bbox[2] - pz};
         const float hi[3] = {A.bbox[3] - px, A.bbox[4] - py, A.bbox[5] - pz};
@@ -1215,10 +1220,10 @@ struct Cell {
     // Removes and returns the entry with the smallest key (best-first), or
     // the last pushed one (depth-first).  The queue is kept by the first wave
     // of a group, which hands the entry to the others.
-    __device__ void pop(uint32_t* e, float* k) {
+    __device__ void pop(uint32_t* e, float* k, bool least = false) {
         uint32_t ee = 0;
         float kk = 0.f;
-        if (lead()) pop_lead(&ee, &kk);
+        if (lead()) pop_lead(&ee, &kk, least || A.traversal != 2);
         if constexpr (G > 1) {
             const uint32_t v[2] = {ee, __float_as_uint(kk)};
             const uint32_t* t = exch(v);
@@ -1229,10 +1234,10 @@ struct Cell {
         *e = ee;
         *k = kk;
     }
-    __device__ void pop_lead(uint32_t* e, float* k) {
+    __device__ void pop_lead(uint32_t* e, float* k, bool least) {
         const int nq = (qn + 63) >> 6;
         int S, L;
-        if (A.traversal == 2) {
+        if (!least) {
             S = (qn - 1) >> 6;
             L = (qn - 1) & 63;
         } else {
@@ -1356,6 +1361,7 @@ struct Cell {
             dw = pw - q.w;
             b = 0.5f * (a2 + dw);
             cand = (uint32_t)ln < nsite && j != self && q.w != -INFINITY && a2 > 0.f;
+            for (int t = 0; t < nwarm; ++t) cand = cand && j != rdl(wsite, t);
             key = cand ? b * __builtin_amdgcn_rsqf(a2) : INFINITY;  // orders candidates only
         }
         auto keep = [&](bool c) -> bool {
@@ -1415,6 +1421,111 @@ struct Cell {
         float4 u = src[0], v = src[1];
         c->lo[0] = u.x; c->lo[1] = u.y; c->lo[2] = u.z; c->wmax = u.w;
         c->hi[0] = v.x; c->hi[1] = v.y; c->hi[2] = v.z; c->ref = __float_as_uint(v.w);
+    }
+
+    // KNN warm start (supplementary Sec. A): before the walk, the K sites
+    // nearest to p_i are found by a best-first walk of the same BVH (queue
+    // keyed by squared distance to the child boxes), and the cell is clipped
+    // by their planes, nearest first.  Lanes 0..K-1 keep the K best squared
+    // distances (best) and sites (bsite); `worst` is the K-th best (infinite
+    // until K are found).  The walk that follows passes over these sites.
+    // Returns kNone or what a clip returned (kEmptied, kOverflow, kRestart).
+    __device__ int knn_warm(int K) {
+        float best = INFINITY;
+        uint32_t bsite = 0u;
+        float worst = INFINITY;
+        qn = 0;
+        auto box_d2 = [&](const NodeChild& c) {
+            const float dx = fmaxf(fmaxf(c.lo[0] - px, px - c.hi[0]), 0.f);
+            const float dy = fmaxf(fmaxf(c.lo[1] - py, py - c.hi[1]), 0.f);
+            const float dz = fmaxf(fmaxf(c.lo[2] - pz, pz - c.hi[2]), 0.f);
+            return fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+        };
+        auto take_leaf = [&](uint32_t ref) {
+            const uint32_t first = leaf_first(ref), cnt = leaf_count(ref);
+            const uint32_t j = first + ((uint32_t)ln < cnt ? (uint32_t)ln : cnt - 1u);
+            const float4 q = A.pts[j];
+            const float dx = q.x - px, dy = q.y - py, dz = q.z - pz;
+            const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+            const bool ok = (uint32_t)ln < cnt && j != self && q.w != -INFINITY && d2 > 0.f;
+            count(kCtrSite, cnt);
+            uint64_t m = ballot(ok && d2 < worst);
+            while (m) {
+                const float c = wmin(((m >> ln) & 1) ? d2 : INFINITY);
+                if (!(c < worst)) break;
+                const uint64_t mm = ballot(((m >> ln) & 1) && d2 == c) & m;
+                const int L = lowest(mm);
+                m &= ~(1ull << L);
+                const uint32_t js = rdl(j, L);
+                // it replaces the worst of the K kept
+                const float wv = wmax((int)ln < K ? best : -INFINITY);
+                const int W = lowest(ballot((int)ln < K && best == wv));
+                if ((int)ln == W) {
+                    best = c;
+                    bsite = js;
+                }
+                worst = wmax((int)ln < K ? best : -INFINITY);
+            }
+        };
+        bool ok = true;
+        {
+            NodeChild c;
+            load_child(A.root, (int)(ln & 1), &c);
+            const float d = box_d2(c);
+            count(kCtrNode, 2);
+            push(A.root << 1, rdl(d, 0));
+            push((A.root << 1) | 1u, rdl(d, 1));
+        }
+        int64_t budget = 4 * A.n + 1024;
+        while (qn > 0 && ok) {
+            if (--budget < 0) break;
+            uint32_t e;
+            float k;
+            pop(&e, &k, true);
+            if (!(k < worst)) break;
+            NodeChild c;
+            load_child(e >> 1, (int)(e & 1), &c);
+            const uint32_t ref = uni(c.ref);
+            if (ref_is_leaf(ref)) {
+                take_leaf(ref);
+                continue;
+            }
+            NodeChild cc;
+            load_child(ref, (int)(ln & 1), &cc);
+            const float d = box_d2(cc);
+            count(kCtrNode, 2);
+            for (int sd = 0; sd < 2; ++sd) {
+                const float dd = rdl(d, sd);
+                if (!(dd < worst)) continue;
+                if (qn >= CAP) {
+                    ok = false;  // queue full: go on with the nearest found so far
+                    break;
+                }
+                push((ref << 1) | (uint32_t)sd, dd);
+            }
+        }
+        qn = 0;
+        // clip by the found sites, nearest first
+        float dd = (int)ln < K ? best : INFINITY;
+        for (int t = 0; t < K; ++t) {
+            const float c = wmin(dd);
+            if (c == INFINITY) break;
+            const int L = lowest(ballot(dd == c));
+            if ((int)ln == L) dd = INFINITY;
+            const uint32_t j = rdl(bsite, L);
+            if ((int)ln == nwarm) wsite = j;
+            ++nwarm;
+            const float4 q = A.pts[j];
+            const float ax = q.x - px, ay = q.y - py, az = q.z - pz;
+            const float a2 = fmaf(ax, ax, fmaf(ay, ay, az * az));
+            const float dw = pw - q.w;
+            const uint64_t t0 = tic();
+            const int r = clip(ax, ay, az, 0.5f * (a2 + dw), 0.5f * (a2 + fabsf(dw)), (int32_t)j, q);
+            toc(kCtrCycClip, t0);
+            if (r == kEmptied || r == kOverflow || r == kRestart) return r;
+            if (r == kChanged) update_bounds();
+        }
+        return kNone;
     }
 
     // The start of Alg. 1.  From the root, the walk first reaches the site's
@@ -1490,6 +1601,11 @@ struct Cell {
         uint32_t done_leaf = 0;
         bool skip_done = false;
         if (!resume && A.leaf_of != nullptr) {
+            if (A.warm_start > 0) {
+                const int rw = knn_warm(A.warm_start);
+                if constexpr (CAP == kHandoffCap) ov_ok = false;
+                if (rw != kNone) return rw;
+            }
             bool deep;
             const int r = own_leaf_start(&done_leaf, &deep);
             if (r != kNone) return r;
@@ -1606,7 +1722,9 @@ struct Cell {
                 }
                 if (tid < nsv()) H.alive[tid] = M.alive[tid];
             }
+            if (tid < kMaxWarm) H.wsite[tid] = tid < nwarm ? wsite : 0u;  // lane t of wave 0 holds site t
             if (tid == 0) {
+                H.nwarm = (uint32_t)nwarm;
                 H.np = (uint32_t)np;
                 H.vhi = (uint32_t)vhi;
                 H.qn = (uint32_t)qn;
@@ -1629,6 +1747,8 @@ struct Cell {
             px = s.x; py = s.y; pz = s.z; pw = s.w;
             flags = H.flags;
             robust = (int)H.robust;
+            nwarm = (int)H.nwarm;
+            wsite = (int)ln < kMaxWarm ? H.wsite[ln] : 0u;
             np = (int)H.np;
             vhi = (int)H.vhi;
             qn = (int)H.qn;

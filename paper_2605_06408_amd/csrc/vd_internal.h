@@ -84,6 +84,7 @@ enum CtrIndex { kCtrClassify = 0, kCtrNewVertex, kCtrNode, kCtrSite, kCtrFinal, 
 // from there instead of starting over: vertices (same numbering, indices
 // packed ten bits each as in the 1024-vertex pass), planes, node queue, and
 // the leaf with its candidates not yet tried.
+constexpr int kMaxWarm = 16;       // largest K of the KNN warm start
 constexpr int kHandoffCap = 1024;   // vertices, planes and queue entries (kTierCap[2])
 constexpr int kHandoffMax = 256;    // cells handed over per build (later ones start over)
 struct Handoff {
@@ -99,6 +100,8 @@ struct Handoff {
     float qk[kHandoffCap];
     uint32_t valid;               // 1: the state above can be resumed
     uint32_t np, vhi, qn, flags, robust, leaf;
+    uint32_t nwarm;               // sites of the KNN warm start (passed over by the leaves)
+    uint32_t wsite[kMaxWarm];
 };
 
 struct ClipArgs {
@@ -114,6 +117,7 @@ struct ClipArgs {
     int leaf_size;
     int culling;              // 1 directional, 2 isotropic
     int traversal;            // 1 best-first, 2 depth-first
+    int warm_start;           // K of the KNN warm start (0: none)
     int precision;            // 1 fp32, 2 mixed
     int tier;                 // 0..3 (capacity kTierCap[tier])
     // work: cells c in [0, count) are list[c] (or c itself when list == null),

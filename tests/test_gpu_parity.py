@@ -160,11 +160,29 @@ def test_leaf_sizes_agree(oracle_mod, leaf):
     _full_parity(oracle_mod, xyz, w, box, min_frac=0.8, leaf_size=leaf)
 
 
-@pytest.mark.parametrize("kw", [dict(culling=2), dict(traversal=2), dict(precision=2)],
-                         ids=["isotropic", "depth_first", "mixed"])
+@pytest.mark.parametrize("kw", [dict(culling=2), dict(traversal=2), dict(precision=2), dict(warm_start=8),
+                                dict(warm_start=16, traversal=2), dict(warm_start=1, culling=1)],
+                         ids=["isotropic", "depth_first", "mixed", "knn_warm8", "knn_warm16_depth_first",
+                              "knn_warm1_directional"])
 def test_ablation_switches_agree(oracle_mod, kw):
     xyz, w, box = wl.clustered(8000, 22)
     _full_parity(oracle_mod, xyz, w, box, min_frac=0.8, **kw)
+
+
+@pytest.mark.parametrize("name", ["power_clustered", "surface"])
+def test_knn_warm_start_agrees(oracle_mod, name):
+    """KNN warm start (the K nearest sites clipped first) on weighted and
+    surface-like inputs, whose cells reach the larger passes (the warm sites
+    travel with a cell handed from one pass to the next)."""
+    xyz, w, box = getattr(wl, name)(20000, 23)
+    _full_parity(oracle_mod, xyz, w, box, min_frac=0.8, warm_start=8)
+
+
+def test_warm_start_option_checked():
+    import paper_2605_06408_amd as vd
+    xyz, _, box = wl.uniform(100, 1)
+    with pytest.raises(vd.VDError):
+        gpu_build(xyz, None, box, warm_start=17)
 
 
 # ------------------------------------------------------------ metamorphic
