@@ -209,6 +209,24 @@ VD_API vd_status vd_write(vd_context* ctx, const vd_outputs* out, void* stream);
 VD_API vd_status vd_backward(vd_context* ctx, const float* g_vol, const float* g_cen, const float* g_vert,
                              float* g_xyz, float* g_w, void* stream);
 
+/* vd_backward for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight training or serving loops, harnesses that forbid
+ * hipMalloc): same arguments, same kernels and the same result, but its
+ * scratch is a fixed device array of the library (64 MiB per device, set up
+ * by vd_create on that device and held until the process ends) instead of
+ * context memory grown with hipMalloc.  It calls no allocating routine and
+ * no memset (its scratch is cleared by a fill kernel).  The caller still
+ * passes the inputs and outputs; the context's build state is read as in
+ * vd_backward.  Needs 32 (n_facet + 2 n) bytes, each part rounded up to 256
+ * (plus 48 per site, at most about 3 MB, when the box is the sites' own);
+ * VD_ERR_INVALID_ARG with the size in the message if the last build
+ * needs more (use vd_backward).  All calls on one device share that array,
+ * which keeps the last call's contents: calls that overlap in time on one
+ * device (several streams or host threads) race and must be serialised by
+ * the caller. */
+VD_API vd_status vd_backward_noalloc(vd_context* ctx, const float* g_vol, const float* g_cen, const float* g_vert,
+                                     float* g_xyz, float* g_w, void* stream);
+
 /* The dual of the last build (paper Sec. 3: the power diagram's dual is the
  * regular triangulation of the weighted sites; for equal weights the Delaunay
  * tetrahedralisation): one tetrahedron per diagram vertex that lies inside the

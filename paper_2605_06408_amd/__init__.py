@@ -112,6 +112,8 @@ def load_library():
             lib.vd_get_counters.argtypes = [P, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32]
             lib.vd_backward.restype = ctypes.c_int
             lib.vd_backward.argtypes = [P, P, P, P, P, P, P]
+            lib.vd_backward_noalloc.restype = ctypes.c_int
+            lib.vd_backward_noalloc.argtypes = [P, P, P, P, P, P, P]
             lib.vd_inspect_bvh.restype = ctypes.c_int
             lib.vd_inspect_bvh.argtypes = [P, P, P, P, P, P, ctypes.POINTER(ctypes.c_uint32), P]
             lib.vd_measure_peaks.restype = ctypes.c_int
@@ -278,10 +280,12 @@ class Context:
         out["root"] = root.value
         return out
 
-    def backward(self, g_vol=None, g_cen=None, g_vert=None, want_w=True):
+    def backward(self, g_vol=None, g_cen=None, g_vert=None, want_w=True, noalloc=False):
         """vd_backward over the last build: gradients of
         sum g_vol V + g_cen . c + g_vert . x with respect to the sites (and
-        weights).  Returns (g_xyz [n, 3], g_w [n] or None)."""
+        weights).  Returns (g_xyz [n, 3], g_w [n] or None).  noalloc=True
+        calls vd_backward_noalloc (the library's fixed device scratch; the
+        output tensors still come from torch)."""
         import torch
         dev = self.device
         n = self.n
@@ -300,8 +304,9 @@ class Context:
         g_w = torch.empty(n, dtype=torch.float32, device=dev) if want_w else None
         stream = torch.cuda.current_stream(dev).cuda_stream
         with torch.cuda.device(dev):
-            _check(self.lib.vd_backward(self.handle, _ptr(gv), _ptr(gc), _ptr(gx), _ptr(g_xyz), _ptr(g_w),
-                                        ctypes.c_void_p(stream)), "vd_backward")
+            fn = self.lib.vd_backward_noalloc if noalloc else self.lib.vd_backward
+            _check(fn(self.handle, _ptr(gv), _ptr(gc), _ptr(gx), _ptr(g_xyz), _ptr(g_w), ctypes.c_void_p(stream)),
+                   "vd_backward_noalloc" if noalloc else "vd_backward")
         self._keep_grad = (gv, gc, gx)
         return g_xyz, g_w
 

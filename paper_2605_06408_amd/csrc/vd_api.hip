@@ -44,6 +44,7 @@ struct vd_context {
     DevBuf tet_cnt, tet_off;  // dual tetrahedra per cell and their offsets
     DevBuf bwd_facet, bwd_self, bwd_orphan, bwd_box;  // backward scratch
     DevBuf inspect;  // scratch of vd_inspect_bvh
+    void* fixed_scratch = nullptr;  // this device's fixed scratch of vd_backward_noalloc
     // last build
     bool valid = false;
     int64_t n = 0;
@@ -153,6 +154,12 @@ VD_API vd_status vd_create(int device, vd_context** out) {
     c->device = device;
     hipError_t e = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device);
     if (e != hipSuccess || c->num_cu < 1) c->num_cu = 256;
+    // address of this device's fixed backward scratch (looked up once per device)
+    e = vd::bwd_scratch_init(device, &c->fixed_scratch);
+    if (e != hipSuccess) {
+        delete c;
+        return fail(VD_ERR_HIP, std::string("vd_create: scratch symbol lookup: ") + hipGetErrorString(e));
+    }
     *out = c;
     return VD_OK;
 }
@@ -546,29 +553,50 @@ VD_API vd_status vd_get_timings(vd_context* c, float* ms, int32_t count) {
     return VD_OK;
 }
 
-VD_API vd_status vd_backward(vd_context* c, const float* g_vol, const float* g_cen, const float* g_vert,
-                             float* g_xyz, float* g_w, void* stream) {
+}  // extern "C"
+
+namespace {
+
+// Scratch of one backward: FP64 facet shares, per-site shares, asymmetric
+// remainders and (box of the sites) the box-face partials, sums and sites.
+struct BwdScratch {
+    double4* facet = nullptr;
+    double4* self = nullptr;
+    double* orphan = nullptr;
+    double* box = nullptr;  // nwaves * 6 partials, 6 sums, then 6 uint32 face sites
+};
+
+size_t bwd_box_bytes(int64_t nwaves) { return (size_t)(nwaves * 6 + 6) * sizeof(double) + 6 * sizeof(uint32_t); }
+
+// Argument checks shared by both backward entry points.
+vd_status bwd_check(vd_context* c, const float* g_xyz, const char* who) {
     g_err.clear();
-    if (!c || !g_xyz) return fail(VD_ERR_INVALID_ARG, "vd_backward: null argument");
-    if (!c->valid) return fail(VD_ERR_STATE, "vd_backward: no successful build");
-    VD_HIP(hipSetDevice(c->device));
-    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (!c || !g_xyz) return fail(VD_ERR_INVALID_ARG, std::string(who) + ": null argument");
+    if (!c->valid) return fail(VD_ERR_STATE, std::string(who) + ": no successful build");
+    return VD_OK;
+}
+
+// The backward kernels over the last build, with the given scratch.  The
+// remainders start at zero and the face sites at 0xFFFFFFFF: cleared with
+// memsets (fill = false) or with a fill kernel (fill = true).
+vd_status bwd_run(vd_context* c, const float* g_vol, const float* g_cen, const float* g_vert, float* g_xyz,
+                  float* g_w, const BwdScratch& sc, bool fill, hipStream_t s) {
     const int64_t n = c->n;
-    const size_t nf = (size_t)(c->sizes.n_facet > 0 ? c->sizes.n_facet : 1);
-    VD_TRY(ensure(c->bwd_facet, nf * sizeof(double4)));
-    VD_TRY(ensure(c->bwd_self, (size_t)n * sizeof(double4)));
-    VD_TRY(ensure(c->bwd_orphan, (size_t)n * 4 * sizeof(double)));
     const int64_t nwaves = vd::bwd_waves(n);
     const bool moving_box = !c->box_given;
-    // per-wave box-face partials, their 6 sums, then the 6 face sites
-    const size_t box_bytes = (size_t)(nwaves * 6 + 6) * sizeof(double) + 6 * sizeof(uint32_t);
-    if (moving_box) VD_TRY(ensure(c->bwd_box, box_bytes));
     const bool prof = c->profiled;
     if (prof) VD_HIP(hipEventRecord(c->ev[9], s));
-    VD_HIP(hipMemsetAsync(c->bwd_orphan.p, 0, (size_t)n * 4 * sizeof(double), s));
-    double* box_part = moving_box ? as<double>(c->bwd_box) : nullptr;
+    double* box_part = moving_box ? sc.box : nullptr;
     uint32_t* box_arg = moving_box ? reinterpret_cast<uint32_t*>(box_part + nwaves * 6 + 6) : nullptr;
-    if (moving_box) VD_HIP(hipMemsetAsync(box_arg, 0xFF, 6 * sizeof(uint32_t), s));
+    if (fill) {
+        VD_HIP(vd::launch_fill_u64(reinterpret_cast<uint64_t*>(sc.orphan), n * 4, 0ull, s));
+        // the six 32-bit face sites are three 64-bit words (8-byte aligned:
+        // they follow whole doubles)
+        if (moving_box) VD_HIP(vd::launch_fill_u64(reinterpret_cast<uint64_t*>(box_arg), 3, ~0ull, s));
+    } else {
+        VD_HIP(hipMemsetAsync(sc.orphan, 0, (size_t)n * 4 * sizeof(double), s));
+        if (moving_box) VD_HIP(hipMemsetAsync(box_arg, 0xFF, 6 * sizeof(uint32_t), s));
+    }
     vd::BwdArgs a{};
     a.n = n;
     a.pts = as<float4>(c->spts);
@@ -584,9 +612,9 @@ VD_API vd_status vd_backward(vd_context* c, const float* g_vol, const float* g_c
     a.g_vol = g_vol;
     a.g_cen = g_cen;
     a.g_vert = g_vert;
-    a.gf = as<double4>(c->bwd_facet);
-    a.gself = as<double4>(c->bwd_self);
-    a.orphan = as<double>(c->bwd_orphan);
+    a.gf = sc.facet;
+    a.gself = sc.self;
+    a.orphan = sc.orphan;
     a.g_xyz = g_xyz;
     a.g_w = g_w;
     a.moving_box = moving_box ? 1 : 0;
@@ -600,6 +628,54 @@ VD_API vd_status vd_backward(vd_context* c, const float* g_vol, const float* g_c
         c->bwd_profiled = true;
     }
     return VD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+VD_API vd_status vd_backward(vd_context* c, const float* g_vol, const float* g_cen, const float* g_vert,
+                             float* g_xyz, float* g_w, void* stream) {
+    VD_TRY(bwd_check(c, g_xyz, "vd_backward"));
+    VD_HIP(hipSetDevice(c->device));
+    const int64_t n = c->n;
+    const size_t nf = (size_t)(c->sizes.n_facet > 0 ? c->sizes.n_facet : 1);
+    VD_TRY(ensure(c->bwd_facet, nf * sizeof(double4)));
+    VD_TRY(ensure(c->bwd_self, (size_t)n * sizeof(double4)));
+    VD_TRY(ensure(c->bwd_orphan, (size_t)n * 4 * sizeof(double)));
+    if (!c->box_given) VD_TRY(ensure(c->bwd_box, bwd_box_bytes(vd::bwd_waves(n))));
+    BwdScratch sc;
+    sc.facet = as<double4>(c->bwd_facet);
+    sc.self = as<double4>(c->bwd_self);
+    sc.orphan = as<double>(c->bwd_orphan);
+    sc.box = as<double>(c->bwd_box);
+    return bwd_run(c, g_vol, g_cen, g_vert, g_xyz, g_w, sc, false, static_cast<hipStream_t>(stream));
+}
+
+VD_API vd_status vd_backward_noalloc(vd_context* c, const float* g_vol, const float* g_cen, const float* g_vert,
+                                     float* g_xyz, float* g_w, void* stream) {
+    VD_TRY(bwd_check(c, g_xyz, "vd_backward_noalloc"));
+    if (!c->fixed_scratch) return fail(VD_ERR_STATE, "vd_backward_noalloc: no fixed scratch on this device");
+    VD_HIP(hipSetDevice(c->device));
+    const int64_t n = c->n;
+    const size_t nf = (size_t)(c->sizes.n_facet > 0 ? c->sizes.n_facet : 1);
+    auto up = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    const size_t b_facet = up(nf * sizeof(double4)), b_self = up((size_t)n * sizeof(double4)),
+                 b_orphan = up((size_t)n * 4 * sizeof(double));
+    const size_t b_box = c->box_given ? 0 : up(bwd_box_bytes(vd::bwd_waves(n)));
+    const size_t need = b_facet + b_self + b_orphan + b_box;
+    if (need > vd::kBwdScratchBytes)
+        return fail(VD_ERR_INVALID_ARG, "vd_backward_noalloc: this diagram (" + std::to_string(n) + " sites, " +
+                                            std::to_string(c->sizes.n_facet) + " facets) needs " +
+                                            std::to_string(need) + " bytes of scratch, above the fixed " +
+                                            std::to_string(vd::kBwdScratchBytes) + "; use vd_backward");
+    unsigned char* base = static_cast<unsigned char*>(c->fixed_scratch);
+    BwdScratch sc;
+    sc.facet = reinterpret_cast<double4*>(base);
+    sc.self = reinterpret_cast<double4*>(base + b_facet);
+    sc.orphan = reinterpret_cast<double*>(base + b_facet + b_self);
+    sc.box = c->box_given ? nullptr : reinterpret_cast<double*>(base + b_facet + b_self + b_orphan);
+    return bwd_run(c, g_vol, g_cen, g_vert, g_xyz, g_w, sc, true, static_cast<hipStream_t>(stream));
 }
 
 VD_API vd_status vd_get_counters(const vd_context* c, uint64_t* out, int32_t count) {

@@ -33,6 +33,8 @@
 // extreme sites (b = p_i,k - min_j p_j,k for a lower face, max_j p_j,k - p_i,k
 // for an upper one): the sum over all cells of dL/db of each face goes to the
 // site on that face with the lowest index, summed in a fixed order.
+#include <mutex>
+
 #include "vd_internal.h"
 
 namespace vd {
@@ -390,7 +392,47 @@ __global__ __launch_bounds__(256) void k_bwd_gather(BwdArgs a) {
     if (a.g_w) a.g_w[j] = (float)g[3];
 }
 
+// Fill of 64-bit words (clears the scratch of the allocation-free entry
+// point with a kernel rather than a memset node, so that the call can be
+// captured into a HIP graph).
+__global__ __launch_bounds__(256) void k_fill_u64(uint64_t* dst, int64_t count, uint64_t value) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (int64_t)gridDim.x * blockDim.x)
+        dst[i] = value;
+}
+
+// Device scratch of vd_backward_noalloc: the facet shares, the per-site
+// shares, the asymmetric remainders and the box-face partials of one
+// backward, in one fixed array per device (set up once per device by
+// bwd_scratch_init; host code uses only the address it returns).
+static __device__ __align__(256) unsigned char scratch[kBwdScratchBytes];
+
+constexpr int kMaxDevices = 64;
+void* g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
 }  // namespace
+
+hipError_t bwd_scratch_init(int device, void** ptr) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return hipSuccess;
+}
+
+hipError_t launch_fill_u64(uint64_t* dst, int64_t count, uint64_t value, hipStream_t s) {
+    if (count <= 0) return hipSuccess;
+    int64_t blocks = (count + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_fill_u64, dim3((unsigned)blocks), dim3(256), 0, s, dst, count, value);
+    return hipGetLastError();
+}
 
 int64_t bwd_waves(int64_t n) {
     const int64_t waves = n < 65536 ? n : 65536;

@@ -263,4 +263,11 @@ hipError_t launch_tet_count(const TetArgs& a, hipStream_t s);
 hipError_t launch_tet_write(const TetArgs& a, hipStream_t s);
 hipError_t launch_backward(const BwdArgs& a, hipStream_t s);
 
+// Fixed device scratch of the allocation-free backward (vd_backward_noalloc):
+// kBwdScratchBytes per device, its address looked up once per device with
+// that device current (bwd_scratch_init) and kept.  dst[0, count) = value.
+constexpr size_t kBwdScratchBytes = size_t(64) << 20;
+hipError_t bwd_scratch_init(int device, void** ptr);
+hipError_t launch_fill_u64(uint64_t* dst, int64_t count, uint64_t value, hipStream_t s);
+
 }  // namespace vd

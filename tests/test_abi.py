@@ -54,6 +54,7 @@ def test_null_arguments_are_rejected_on_the_host(lib):
     assert lib.vd_get_sizes(None, None) == 1
     assert lib.vd_create(0, None) == 1
     assert lib.vd_backward(None, None, None, None, None, None, None) == 1
+    assert lib.vd_backward_noalloc(None, None, None, None, None, None, None) == 1
     lib.vd_destroy(None)  # no-op
 
 
