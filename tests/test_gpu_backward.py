@@ -336,11 +336,17 @@ def test_config5_finite_differences(oracle_mod):
     need = np.unique(np.concatenate([sites, first["nbr"]]))
     res = oracle.cells(xyz, w, box, ids=need)
     row = {int(i): t for t, i in enumerate(need)}
-    ok = _same_topology_sites(d, res, sites)
-    cert = [int(k) for k in ok
-            if all(res["margin"][row[int(j)]] >= 1e-5
-                   for j in np.concatenate([[k], res["nbr"][res["nbr_off"][row[int(k)]]:res["nbr_off"][row[int(k)] + 1]]]))]
-    assert len(cert) >= 0.8 * len(sites), (len(cert), len(sites))
+    ok = set(_same_topology_sites(d, res, sites).tolist())
+    # certified: the site's cell and its neighbours' cells are at least
+    # 1e-5 from a change of combinatorics (tight clusters leave many below)
+    certified = [int(k) for k in sites
+                 if all(res["margin"][row[int(j)]] >= 1e-5
+                        for j in np.concatenate([[k], res["nbr"][res["nbr_off"][row[int(k)]]:res["nbr_off"][row[int(k)] + 1]]]))]
+    cert = [k for k in certified if k in ok]
+    print("config 5: %d sampled sites, %d certified with their neighbours, %d of those with the GPU's combinatorics"
+          % (len(sites), len(certified), len(cert)))
+    assert len(certified) >= 0.6 * len(sites), (len(certified), len(sites))
+    assert len(cert) >= 0.99 * len(certified), (len(cert), len(certified))
     x64, w64 = xyz.astype(np.float64), w.astype(np.float64)
     S = oracle.Session(x64, w64, box)
 
@@ -406,22 +412,31 @@ def test_config5_volume_weight_closed_form():
     _, g_w = ctx.backward(torch.from_numpy(g_vol).cuda(), None, None)
     g_w = g_w.cpu().numpy().astype(np.float64)
     g = to_numpy(d, np.array(chosen))
+    # The areas come from the FP32 output vertices: each coordinate carries
+    # up to 2^-24 |x| of rounding, so a ring's area is known to within
+    # 2^-23 max|x| times its perimeter (each edge moves with both ends);
+    # the backward itself works in FP64.  Each comparison is held to 1e-6 of
+    # sum_j A_ij / (2 D_ij) plus that area uncertainty over 2 D_ij.
     worst = 0.0
     for t, i in enumerate(chosen):
-        own, err = 0.0, 0.0
+        own, own_unc, excess = 0.0, 0.0, 0.0
         for f in range(g["facet_off"][t], g["facet_off"][t + 1]):
             j = int(g["facet_nbr"][f])
             if j < 0:
                 continue
             ring = g["vert"][g["fv"][g["fv_off"][f]:g["fv_off"][f + 1]]].astype(np.float64)
+            unc = 2.0 ** -23 * float(np.abs(ring).max()) * float(
+                sum(np.linalg.norm(ring[(q + 1) % len(ring)] - ring[q]) for q in range(len(ring))))
             ring = ring - ring[0]
             area = 0.5 * np.linalg.norm(sum(np.cross(ring[q], ring[(q + 1) % len(ring)]) for q in range(len(ring))))
             D = float(np.linalg.norm(xyz[j].astype(np.float64) - xyz[i].astype(np.float64)))
             own += area / (2 * D)
+            own_unc += unc / (2 * D)
             # i is the only chosen cell next to j
-            err = max(err, abs(g_w[j] + area / (2 * D)))
-        err = max(err, abs(g_w[i] - own))
-        worst = max(worst, err / own)
-    print("closed form dV/dw on %d cells: max error %.2e of sum_j A_ij / (2 D_ij)" % (len(chosen), worst))
+            excess = max(excess, abs(g_w[j] + area / (2 * D)) - unc / (2 * D))
+        excess = max(excess, abs(g_w[i] - own) - own_unc)
+        worst = max(worst, excess / own)
+    print("closed form dV/dw on %d cells: max error beyond the FP32 area uncertainty %.2e of sum_j A_ij / (2 D_ij)"
+          % (len(chosen), worst))
     assert len(chosen) == 300
-    assert worst <= 1e-4
+    assert worst <= 1e-6
