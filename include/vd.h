@@ -50,6 +50,8 @@ typedef enum {
 #define VD_FLAG_LARGE 4u      /* built by a larger-capacity pass */
 #define VD_FLAG_UNCERTAIN 8u  /* FP32 clipping met an inconsistent configuration */
 #define VD_FLAG_FAILED 16u    /* cell exceeded every capacity; outputs empty */
+#define VD_FLAG_PERTURBED 32u /* some exact tie of this cell was decided by the
+                                 symbolic perturbation (vd_options.perturb) */
 
 /* Options; pass NULL for the defaults.  Zero in any field means its default. */
 typedef struct vd_options {
@@ -67,7 +69,22 @@ typedef struct vd_options {
     int32_t warm_start; /* K = 1..16: KNN warm start (supplementary Sec. A): each cell is
                            first clipped by its K nearest sites, found by a best-first
                            query of the same BVH; 0 = none (default) */
-    int32_t reserved;
+    int32_t perturb;    /* 1 = symbolic perturbation of exact degeneracies: signs FP32
+                           cannot decide are re-evaluated in FP64 as in the mixed form
+                           (precision is taken as 2), then, where that evaluation is
+                           exact (checked per operation; true for short dyadic
+                           coordinates such as lattices) and zero, decided as for the
+                           weights w_k + d^(k+1), d infinitesimal, k the original index
+                           (Simulation of Simplicity, Edelsbrunner and Muecke 1990).
+                           The result is then the diagram of that perturbed input, in
+                           general position: every vertex joins three planes, and at
+                           a vertex of five or more co-spherical sites the dual is a
+                           proper regular triangulation.  Its geometry is the limit
+                           d -> 0 (zero-area facets and coincident vertices where the
+                           input is degenerate; such facets are listed and their
+                           sites are neighbours).  Signs the checked evaluation cannot
+                           settle stay flagged VD_FLAG_UNCERTAIN.  0 = off (default):
+                           exact ties are kept inside (Sec. B's convention) */
 } vd_options;
 
 /* Phases reported by vd_get_timings (milliseconds, HIP events on `stream`). */
@@ -119,6 +136,7 @@ typedef struct vd_sizes {
     int64_t n_huge;     /* cells that needed the 16384-vertex pass */
     int64_t n_resumed;  /* of those, cells it took over from the 1024-vertex
                            pass where that one stopped, rather than anew */
+    int64_t n_perturbed;/* cells flagged VD_FLAG_PERTURBED */
 } vd_sizes;
 
 /* Output arrays: caller-owned device memory, sized from vd_sizes.  Rows are

@@ -21,6 +21,14 @@ import math
 from fractions import Fraction as Q
 
 
+def _weight(w, j):
+    """Weight j as an exact rational: FP32 inputs, or Fractions as given (a
+    test may pass exactly perturbed weights)."""
+    if w is None:
+        return Q(0)
+    return w[j] if isinstance(w[j], Q) else Q(float(w[j]))
+
+
 def _losers(xyz, w):
     """Sites sharing a position with a heavier site (or an equally heavy one
     of lower index): their cells are empty and their planes are implied by the
@@ -31,7 +39,7 @@ def _losers(xyz, w):
         groups.setdefault(tuple(float(c) for c in xyz[j]), []).append(j)
     for g in groups.values():
         if len(g) > 1:
-            win = max(g, key=lambda j: (float(w[j]) if w is not None else 0.0, -j))
+            win = max(g, key=lambda j: (_weight(w, j), -j))
             out.update(j for j in g if j != win)
     return out
 
@@ -40,7 +48,7 @@ def _planes(xyz, w, box, i):
     import numpy as np
     box = [float(np.float32(v)) for v in box]  # the clip box is an FP32 input
     p = [Q(float(c)) for c in xyz[i]]
-    wi = Q(float(w[i])) if w is not None else Q(0)
+    wi = _weight(w, i)
     pl = []
     for ax in range(3):
         lo = [Q(0)] * 3
@@ -57,7 +65,7 @@ def _planes(xyz, w, box, i):
         d2 = sum(c * c for c in a)
         if d2 == 0:
             continue
-        wj = Q(float(w[j])) if w is not None else Q(0)
+        wj = _weight(w, j)
         pl.append((a, (d2 + wi - wj) / 2, j))
     coincident_empty = i in losers
     return p, pl, coincident_empty

@@ -24,6 +24,7 @@ FLAG_FP64 = 2
 FLAG_LARGE = 4
 FLAG_UNCERTAIN = 8
 FLAG_FAILED = 16
+FLAG_PERTURBED = 32
 
 PRECISION_FP32 = 1
 PRECISION_MIXED = 2
@@ -53,13 +54,13 @@ class VDError(RuntimeError):
 class Options(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("leaf_size", ctypes.c_int32), ("culling", ctypes.c_int32),
                 ("traversal", ctypes.c_int32), ("profile", ctypes.c_int32), ("counters", ctypes.c_int32),
-                ("warm_start", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("warm_start", ctypes.c_int32), ("perturb", ctypes.c_int32)]
 
 
 class Sizes(ctypes.Structure):
     _fields_ = [(k, ctypes.c_int64) for k in ("n", "n_nbr", "n_facet", "n_vert", "n_fv", "n_empty", "n_large",
                                                "n_uncertain", "n_failed", "n_fp64", "n_huge",
-                                               "n_resumed")]
+                                               "n_resumed", "n_perturbed")]
 
     def as_dict(self) -> dict:
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -165,7 +166,7 @@ class Context:
 
     def build_sizes(self, xyz, w=None, bbox=None, precision=PRECISION_FP32, leaf_size=0,
                     culling=CULLING_BALLS, traversal=TRAVERSAL_BEST_FIRST, allow_failed=False,
-                    profile=False, counters=False, warm_start=0) -> Sizes:
+                    profile=False, counters=False, warm_start=0, perturb=0) -> Sizes:
         """Run vd_build only (the diagram stays in the context)."""
         import torch
         if not (xyz.is_cuda and xyz.dtype == torch.float32 and xyz.dim() == 2 and xyz.shape[1] == 3):
@@ -182,7 +183,8 @@ class Context:
             if len(vals) != 6:
                 raise ValueError("bbox must have 6 entries")
             hb = (ctypes.c_float * 6)(*vals)
-        opt = Options(precision, leaf_size, culling, traversal, int(profile), int(counters), int(warm_start))
+        opt = Options(precision, leaf_size, culling, traversal, int(profile), int(counters), int(warm_start),
+                      int(perturb))
         sz = Sizes()
         stream = torch.cuda.current_stream(self.device).cuda_stream
         with torch.cuda.device(self.device):

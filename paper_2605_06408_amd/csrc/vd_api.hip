@@ -204,6 +204,8 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
         return fail(VD_ERR_INVALID_ARG, "vd_build: n must be in [1, " + std::to_string(vd::kMaxSites) + "]");
     vd_options o{};
     if (opt) o = *opt;
+    if (o.perturb < 0 || o.perturb > 1) return fail(VD_ERR_INVALID_ARG, "vd_build: perturb must be 0 or 1");
+    if (o.perturb) o.precision = 2;  // ties reach the exact test through the FP64 re-evaluation
     if (o.precision == 0) o.precision = 1;
     if (o.leaf_size == 0) o.leaf_size = vd::kDefaultLeaf;
     if (o.culling == 0) o.culling = 3;
@@ -316,6 +318,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     a.traversal = o.traversal;
     a.warm_start = o.warm_start;
     a.precision = o.precision;
+    a.perturb = o.perturb;
     a.loc = as<uint32_t>(c->loc);
     a.cnt_v = as<uint32_t>(c->cnt_v);
     a.cnt_f = as<uint32_t>(c->cnt_f);
@@ -415,6 +418,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     z.n_fp64 = (int64_t)st[vd::kStatFP64];
     z.n_huge = c->tier_slots[3];
     z.n_resumed = (int64_t)st[vd::kStatResumed];
+    z.n_perturbed = (int64_t)st[vd::kStatPerturbed];
     c->sizes = z;
     c->n = n;
     c->order = order;

@@ -254,10 +254,13 @@ struct P64 {
 // kLds: the per-cell arrays are in LDS (else in global memory).  kCount:
 // count work units and cycles (a separate instantiation, so the timed
 // kernels carry no counting code).  G: waves building the cell together
-// (one in the register tiers).  Every wave of a group holds the same copy of
-// the cell-wide scalars (site, bounds, plane and queue counts, flags) and
-// changes it the same way, from values every wave has seen.
-template <int VPL, bool kLds, bool kCount, int G = 1>
+// (one in the register tiers).  kSoS: exact ties decided by the symbolic
+// perturbation (its own instantiation: the checked exact evaluation would
+// otherwise cost the default kernels registers).  Every wave of a group
+// holds the same copy of the cell-wide scalars (site, bounds, plane and
+// queue counts, flags) and changes it the same way, from values every wave
+// has seen.
+template <int VPL, bool kLds, bool kCount, int G = 1, bool kSoS = false>
 struct Cell {
     static_assert(G == 1 || !Tier<VPL>::kReg, "wave groups need the vertex state in memory");
     using T = Tier<VPL>;
@@ -696,6 +699,107 @@ struct Cell {
         return s > 0 ? 1 : -1;
     }
 
+    // ------------------------------------------------------------ exact ties
+    // Side of the vertex with planes t w.r.t. the plane of site hsite (code
+    // hcode) when the FP64 filter cannot decide it: the test is evaluated
+    // again in FP64 with every operation checked to be exact (the error of
+    // each product by a fused multiply-add, of each sum by the two-sum
+    // identity).  That holds for inputs with short dyadic coordinates, such
+    // as lattices, which is where exact ties occur.  If the value is exact
+    // and non-zero its sign decides (+-1).  If it is exactly zero the weights
+    // are perturbed symbolically, w_k -> w_k + d^(k+1) for infinitesimal d
+    // and original index k (Simulation of Simplicity): the test S is linear
+    // in the plane offsets b = (|a|^2 + w_i - w_x) / 2, hence in the weights,
+    // and its sign is that of the weight derivative of lowest original index
+    // among the non-zero ones (+-2).  Returns 0 if some operation was not
+    // exact (the sign stays undecided).
+    //   S = det (a_h . y - b_h) = b_A a_h.(B x C) + b_B a_h.(C x A) + b_C a_h.(A x B) - b_h det
+    //   dS/dw_x = -a_h.cross_X / 2 (X the plane of site x), dS/dw_m = det / 2
+    //   (m the site of h), dS/dw_i = (sum of a_h.cross_X over site planes - det) / 2;
+    // the vertex is outside iff S det > 0.
+    struct PX {
+        double a[3], b;
+        uint32_t orig;  // original index of the plane's site (box faces: none)
+        bool site;
+    };
+    __device__ static double xmul(double a, double b, bool& ok) {
+        const double p = a * b;
+        ok &= fma(a, b, -p) == 0.0;
+        return p;
+    }
+    __device__ static double xadd(double a, double b, bool& ok) {
+        const double s = a + b;
+        const double bv = s - a;
+        ok &= ((a - (s - bv)) + (b - bv)) == 0.0;
+        return s;
+    }
+    __device__ PX plane_exact(int32_t code, float4 site, bool& ok) const {
+        PX r;
+        const double q[3] = {(double)px, (double)py, (double)pz};
+        if (code < 0) {
+            const int c = -code - 1, ax = c >> 1, side = c & 1;
+            r.a[0] = r.a[1] = r.a[2] = 0.0;
+            r.a[ax] = side ? 1.0 : -1.0;
+            r.b = side ? xadd((double)A.bbox[3 + ax], -q[ax], ok) : xadd(q[ax], -(double)A.bbox[ax], ok);
+            r.orig = 0u;
+            r.site = false;
+        } else {
+            r.a[0] = xadd((double)site.x, -q[0], ok);
+            r.a[1] = xadd((double)site.y, -q[1], ok);
+            r.a[2] = xadd((double)site.z, -q[2], ok);
+            double s2 = xadd(xadd(xmul(r.a[0], r.a[0], ok), xmul(r.a[1], r.a[1], ok), ok),
+                             xmul(r.a[2], r.a[2], ok), ok);
+            r.b = 0.5 * xadd(s2, xadd((double)pw, -(double)site.w, ok), ok);
+            r.orig = cold_args()->order[code];
+            r.site = true;
+        }
+        return r;
+    }
+    __device__ static void xcross(const double* u, const double* v, double* o, bool& ok) {
+        o[0] = xadd(xmul(u[1], v[2], ok), -xmul(u[2], v[1], ok), ok);
+        o[1] = xadd(xmul(u[2], v[0], ok), -xmul(u[0], v[2], ok), ok);
+        o[2] = xadd(xmul(u[0], v[1], ok), -xmul(u[1], v[0], ok), ok);
+    }
+    __device__ static double xdot(const double* u, const double* v, bool& ok) {
+        return xadd(xadd(xmul(u[0], v[0], ok), xmul(u[1], v[1], ok), ok), xmul(u[2], v[2], ok), ok);
+    }
+    __device__ int side_exact(W t, int32_t hcode, float4 hsite) const {
+        bool ok = true;
+        const PX P0 = plane_exact(M.pcode[T::fld(t, 0)], M.psite[T::fld(t, 0)], ok);
+        const PX P1 = plane_exact(M.pcode[T::fld(t, 1)], M.psite[T::fld(t, 1)], ok);
+        const PX P2 = plane_exact(M.pcode[T::fld(t, 2)], M.psite[T::fld(t, 2)], ok);
+        const PX H = plane_exact(hcode, hsite, ok);
+        double cr[3][3];
+        xcross(P1.a, P2.a, cr[0], ok);
+        xcross(P2.a, P0.a, cr[1], ok);
+        xcross(P0.a, P1.a, cr[2], ok);
+        const double det = xdot(P0.a, cr[0], ok);
+        const double hb[3] = {xdot(H.a, cr[0], ok), xdot(H.a, cr[1], ok), xdot(H.a, cr[2], ok)};
+        double S = xadd(xadd(xmul(P0.b, hb[0], ok), xmul(P1.b, hb[1], ok), ok),
+                        xadd(xmul(P2.b, hb[2], ok), -xmul(H.b, det, ok), ok), ok);
+        if (!ok || det == 0.0) return 0;
+        const int sd = det > 0.0 ? 1 : -1;
+        if (S != 0.0) return (S > 0.0 ? 1 : -1) == sd ? 1 : -1;
+        // exact tie: the lowest original index with a non-zero weight derivative
+        uint32_t best = H.orig;
+        int sgn = sd;  // dS/dw_m = det / 2
+        double own = -det;
+        const PX* X[3] = {&P0, &P1, &P2};
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+            if (!X[r]->site) continue;
+            own = xadd(own, hb[r], ok);
+            if (hb[r] != 0.0 && X[r]->orig < best) {
+                best = X[r]->orig;
+                sgn = hb[r] > 0.0 ? -1 : 1;  // dS/dw_x = -a_h.cross_X / 2
+            }
+        }
+        if (!ok) return 0;
+        const uint32_t self_orig = cold_args()->order[self];
+        if (own != 0.0 && self_orig < best) sgn = own > 0.0 ? 1 : -1;
+        return sgn == sd ? 2 : -2;
+    }
+
     // ------------------------------------------------------------ clip
     // mode 0: plain FP32 signs; 1: doubtful signs re-evaluated in FP64;
     // 2: doubtful signs taken as inside; 3: every sign evaluated in FP64.
@@ -765,13 +869,19 @@ struct Cell {
             P64 h = plane64(hcode, hsite);
             anyo = false;
             allo = true;
-            bool uns = false;
+            bool uns = false, pert = false;
 #pragma unroll
             for (int s = (kReg ? 0 : lo); s < (kReg ? VPL : min(hi, ns)); ++s) {
                 bool o = (R[s] >> ln) & 1;
-                bool unsure = false;
+                bool unsure = false, tie = false;
                 if (amb[s]) {
                     int sg = side64(vt[s], h);
+                    if constexpr (kSoS) {
+                        if (sg == 0) {
+                            sg = side_exact(vt[s], hcode, hsite);
+                            tie = sg == 2 || sg == -2;
+                        }
+                    }
                     o = sg > 0;
                     unsure = sg == 0;
                 }
@@ -780,21 +890,25 @@ struct Cell {
                 anyo |= r != 0;
                 allo &= r == alive[s];
                 uns |= ballot(unsure) != 0;
+                pert |= ballot(tie) != 0;
             }
             if constexpr (G > 1) {
-                const uint32_t v[3] = {anyo ? 1u : 0u, allo ? 1u : 0u, uns ? 1u : 0u};
+                const uint32_t v[4] = {anyo ? 1u : 0u, allo ? 1u : 0u, uns ? 1u : 0u, pert ? 1u : 0u};
                 const uint32_t* t = exch(v);
                 anyo = false;
                 allo = true;
                 uns = false;
+                pert = false;
 #pragma unroll
                 for (int w = 0; w < G; ++w) {
                     anyo |= t[w * 8] != 0;
                     allo &= t[w * 8 + 1] != 0;
                     uns |= t[w * 8 + 2] != 0;
+                    pert |= t[w * 8 + 3] != 0;
                 }
             }
             if (uns) flags |= kFlagUncertain;
+            if (pert) flags |= kFlagPerturbed;
         }
         *any_out = anyo;
         *all_out = allo;
@@ -2005,15 +2119,15 @@ struct Cell {
 
 // The work loop shared by every tier (per wave, or per wave group with gx
 // its exchange tables).
-template <int VPL, bool kLds, bool kCount, int G = 1>
+template <int VPL, bool kLds, bool kCount, int G = 1, bool kSoS = false>
 __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
     KArgs* ka = cold_args();
     // the input checks (non-finite values, a flat box) ran before this pass:
     // on such input no cell is built
     if (*ka->err != 0u) return;
-    Cell<VPL, kLds, kCount, G> C(M, A, gx);
+    Cell<VPL, kLds, kCount, G, kSoS> C(M, A, gx);
     const uint32_t count = ka->list ? *ka->list_count : (uint32_t)A.n;
-    unsigned long long st_empty = 0, st_large = 0, st_unc = 0, st_fail = 0, st_fp64 = 0, st_res = 0;
+    unsigned long long st_empty = 0, st_large = 0, st_unc = 0, st_fail = 0, st_fp64 = 0, st_res = 0, st_pert = 0;
     // Cells are split into kWorkRanges contiguous (Morton-ordered) ranges, one
     // per XCD: the waves of workgroup b take chunks of their own range b % 8
     // first, so neighbouring cells (which walk the same nodes and sites) share
@@ -2130,6 +2244,7 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
         st_large += (C.flags & kFlagLarge) ? 1 : 0;
         st_unc += (C.flags & kFlagUncertain) ? 1 : 0;
         st_fp64 += (C.flags & kFlagFP64) ? 1 : 0;
+        st_pert += (C.flags & kFlagPerturbed) ? 1 : 0;
     }
     if (C.ln == 0 && C.lead()) {
         ka = cold_args();
@@ -2142,6 +2257,7 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
         if (st_fail) atomicAdd(&ka->stats[kStatFailed], st_fail);
         if (st_fp64) atomicAdd(&ka->stats[kStatFP64], st_fp64);
         if (st_res) atomicAdd(&ka->stats[kStatResumed], st_res);
+        if (st_pert) atomicAdd(&ka->stats[kStatPerturbed], st_pert);
     }
 }
 
@@ -2149,10 +2265,10 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
 // block.  Register budgets: the 64-vertex pass is held to 128 registers for
 // 4 waves per SIMD, the 256-vertex pass to 256 for 2 (a few spills cost less
 // than the lost occupancy: both passes issue VALU work back to back).
-template <int VPL, int WAVES, bool kCount>
+template <int VPL, int WAVES, bool kCount, bool kSoS = false>
 __global__ __launch_bounds__(64 * WAVES, VPL == 1 ? 4 : 2) void k_clip(ClipArgs A) {
     __shared__ WaveMem<VPL> mem[WAVES];
-    run_cells<VPL, true, kCount>(mem[threadIdx.x >> 6], A, nullptr);
+    run_cells<VPL, true, kCount, 1, kSoS>(mem[threadIdx.x >> 6], A, nullptr);
 }
 
 // Waves per cell in the 1024-vertex (LDS) and 16384-vertex (arena) tiers.
@@ -2161,20 +2277,20 @@ constexpr int kGroupArena = 8;
 
 // 1024-vertex tier: the kGroupLds waves of a block build one cell, its
 // arrays in LDS (one block per CU).
-template <bool kCount>
+template <bool kCount, bool kSoS = false>
 __global__ __launch_bounds__(64 * kGroupLds, 1) void k_clip_lds(ClipArgs A) {
     __shared__ WaveMem<16> mem;
     __shared__ uint32_t gx[2 * kGroupLds * 8];
-    run_cells<16, true, kCount, kGroupLds>(mem, A, gx);
+    run_cells<16, true, kCount, kGroupLds, kSoS>(mem, A, gx);
 }
 
 // 16384-vertex tier: the kGroupArena waves of a block build one cell, its
 // arrays in arena[blockIdx.x].
 constexpr int kArenaVPL = kTierCap[3] / 64;
-template <bool kCount>
+template <bool kCount, bool kSoS = false>
 __global__ __launch_bounds__(64 * kGroupArena) void k_clip_arena(ClipArgs A, WaveMem<kArenaVPL>* arena) {
     __shared__ uint32_t gx[2 * kGroupArena * 8];
-    run_cells<kArenaVPL, false, kCount, kGroupArena>(arena[blockIdx.x], A, gx);
+    run_cells<kArenaVPL, false, kCount, kGroupArena, kSoS>(arena[blockIdx.x], A, gx);
 }
 
 static_assert(kTierCap[0] == 64 && kTierCap[1] == 256 && kTierCap[2] == 1024,
@@ -2208,20 +2324,20 @@ int clip_grid_workers(int tier, int num_cu) {
     return per_cu * num_cu;
 }
 
-template <bool kCount>
+template <bool kCount, bool kSoS>
 void launch_tier(const ClipArgs& a, int workers, void* arena, hipStream_t s) {
     switch (a.tier) {
         case 0:
-            hipLaunchKernelGGL((k_clip<1, 4, kCount>), dim3((workers + 3) / 4), dim3(256), 0, s, a);
+            hipLaunchKernelGGL((k_clip<1, 4, kCount, kSoS>), dim3((workers + 3) / 4), dim3(256), 0, s, a);
             break;
         case 1:
-            hipLaunchKernelGGL((k_clip<4, 2, kCount>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
+            hipLaunchKernelGGL((k_clip<4, 2, kCount, kSoS>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
             break;
         case 2:
-            hipLaunchKernelGGL((k_clip_lds<kCount>), dim3(workers), dim3(64 * kGroupLds), 0, s, a);
+            hipLaunchKernelGGL((k_clip_lds<kCount, kSoS>), dim3(workers), dim3(64 * kGroupLds), 0, s, a);
             break;
         default:
-            hipLaunchKernelGGL((k_clip_arena<kCount>), dim3(workers), dim3(64 * kGroupArena), 0, s, a,
+            hipLaunchKernelGGL((k_clip_arena<kCount, kSoS>), dim3(workers), dim3(64 * kGroupArena), 0, s, a,
                                static_cast<WaveMem<kArenaVPL>*>(arena));
             break;
     }
@@ -2230,8 +2346,10 @@ void launch_tier(const ClipArgs& a, int workers, void* arena, hipStream_t s) {
 hipError_t launch_clip(const ClipArgs& a, int workers, void* arena, hipStream_t s) {
     if (a.tier >= 3 && !arena) return hipErrorInvalidValue;
     if (workers < 1) return hipErrorInvalidValue;
-    if (a.ctr) launch_tier<true>(a, workers, arena, s);
-    else launch_tier<false>(a, workers, arena, s);
+    // the perturbed build has no counting instantiation (counters stay zero)
+    if (a.perturb) launch_tier<false, true>(a, workers, arena, s);
+    else if (a.ctr) launch_tier<true, false>(a, workers, arena, s);
+    else launch_tier<false, false>(a, workers, arena, s);
     return hipGetLastError();
 }
 

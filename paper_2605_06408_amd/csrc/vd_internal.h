@@ -71,10 +71,12 @@ struct Stage {
 __host__ __device__ inline uint32_t make_loc(uint32_t tier, uint32_t slot) { return (tier << 30) | slot; }
 
 // Per-cell flag bits (mirror vd.h)
-constexpr uint32_t kFlagEmpty = 1u, kFlagFP64 = 2u, kFlagLarge = 4u, kFlagUncertain = 8u, kFlagFailed = 16u;
+constexpr uint32_t kFlagEmpty = 1u, kFlagFP64 = 2u, kFlagLarge = 4u, kFlagUncertain = 8u, kFlagFailed = 16u,
+                   kFlagPerturbed = 32u;
 
 // Build statistics accumulated by the clip kernels (device, uint64 each).
-enum StatIndex { kStatEmpty = 0, kStatLarge, kStatUncertain, kStatFailed, kStatFP64, kStatResumed, kStatCount };
+enum StatIndex { kStatEmpty = 0, kStatLarge, kStatUncertain, kStatFailed, kStatFP64, kStatResumed, kStatPerturbed,
+                 kStatCount };
 // Work counters (mirror VD_CTR_* in vd.h).
 enum CtrIndex { kCtrClassify = 0, kCtrNewVertex, kCtrNode, kCtrSite, kCtrFinal, kCtrClip, kCtrEffective, kCtrLeaf,
                 kCtrBall, kCtrFP64, kCtrCycTraverse, kCtrCycLeaf, kCtrCycClip, kCtrCycFinal, kCtrCount };
@@ -119,6 +121,7 @@ struct ClipArgs {
     int traversal;            // 1 best-first, 2 depth-first
     int warm_start;           // K of the KNN warm start (0: none)
     int precision;            // 1 fp32, 2 mixed
+    int perturb;              // 1: exact ties decided by symbolic perturbation of the weights
     int tier;                 // 0..3 (capacity kTierCap[tier])
     // work: cells c in [0, count) are list[c] (or c itself when list == null),
     // split into kWorkRanges contiguous ranges with one counter each (zeroed)
