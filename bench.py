@@ -414,6 +414,13 @@ def main():
         if args.precision == 1 and not args.no_cpu_baseline:
             main_leg["diagrams"] = {"fp32": ctx.build(tx, tw, bbox, **kw),
                                     "mixed": mctx.build(tx, tw, bbox, **dict(kw, precision=2))}
+        del mctx
+        # the symbolic perturbation of exact ties (mixed signs plus the checked
+        # exact evaluation) on the same workload
+        log("perturbed leg (%s)" % args.config)
+        prep, _, _ = run_leg(args.config, xyz, w, box, dict(kw, perturb=1), st, wu, "perturbed")
+        out["perturbed"] = {k2: prep[k2] for k2 in ("value", "ms_per_step", "kernel_ms_build")}
+        out["perturbed"]["cells_perturbed"] = prep["sizes"]["n_perturbed"]
         out["legs"] = {}
         for name in ("surface_20m", "power_uniform_1m"):
             log("leg %s" % name)

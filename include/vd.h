@@ -134,7 +134,7 @@ typedef struct vd_sizes {
     int64_t n_failed;   /* cells flagged VD_FLAG_FAILED (status VD_ERR_CAPACITY) */
     int64_t n_fp64;     /* cells with at least one FP64 re-evaluation */
     int64_t n_huge;     /* cells that needed the 16384-vertex pass */
-    int64_t n_resumed;  /* of those, cells it took over from the 1024-vertex
+    int64_t n_resumed;  /* cells a larger pass took over from the previous
                            pass where that one stopped, rather than anew */
     int64_t n_perturbed;/* cells flagged VD_FLAG_PERTURBED */
 } vd_sizes;

@@ -40,7 +40,8 @@ struct vd_context {
     DevBuf lists[vd::kTiers];  // lists[t]: cells handed on to tier t (t >= 1)
     DevBuf st_vert[vd::kTiers], st_tri64[vd::kTiers], st_code[vd::kTiers], st_fsize[vd::kTiers], st_fv[vd::kTiers];
     DevBuf arena;  // per-worker cell arrays of the last (16384-vertex) pass
-    DevBuf handoff;  // cells the 1024-vertex pass hands to the last one
+    DevBuf hand[vd::kTiers - 1];  // hand[t]: states of the cells the pass of tier t hands to the next
+    uint32_t seen[vd::kTiers] = {};  // largest cell count of each pass met so far (sizes its buffers)
     DevBuf tet_cnt, tet_off;  // dual tetrahedra per cell and their offsets
     DevBuf bwd_facet, bwd_self, bwd_orphan, bwd_box;  // backward scratch
     DevBuf inspect;  // scratch of vd_inspect_bvh
@@ -172,11 +173,12 @@ VD_API void vd_destroy(vd_context* c) {
                      &c->child, &c->pint, &c->pleaf, &c->range, &c->counters, &c->nodes, &c->hist, &c->stmp,
                      &c->bbox, &c->bpart, &c->misc, &c->loc, &c->cnt_v, &c->cnt_f, &c->cnt_n, &c->vol, &c->cen,
                      &c->flags, &c->offv, &c->offf, &c->offn, &c->scan_tmp, &c->stats,
-                     &c->ctr, &c->arena, &c->handoff, &c->tet_cnt, &c->tet_off, &c->bwd_facet, &c->bwd_self,
+                     &c->ctr, &c->arena, &c->tet_cnt, &c->tet_off, &c->bwd_facet, &c->bwd_self,
                      &c->bwd_orphan, &c->bwd_box, &c->inspect};
     for (DevBuf* b : all) release(*b);
     if (c->ev_ready)
         for (hipEvent_t e : c->ev) (void)hipEventDestroy(e);
+    for (int t = 0; t + 1 < vd::kTiers; ++t) release(c->hand[t]);
     for (int t = 0; t < vd::kTiers; ++t) {
         release(c->lists[t]);
         release(c->st_vert[t]);
@@ -268,8 +270,9 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     VD_TRY(ensure(c->ctr, vd::kTiers * vd::kCtrCount * sizeof(unsigned long long)));
     VD_TRY(ensure_stage(c, 0, n));
 
-    // misc: [0] error bits, [4 + t] list count of tier t >= 1, [16 + 8 t ..] the
-    // kWorkRanges work counters of tier t
+    // misc: [0] error bits, [1] cells left undone for want of slots, [4 + t]
+    // list count of tier t >= 1, [16 + 8 t ..] the kWorkRanges work counters
+    // of tier t
     uint32_t* misc = as<uint32_t>(c->misc);
     if (prof) VD_HIP(hipEventRecord(c->ev[0], s));
     VD_HIP(hipMemsetAsync(misc, 0, kMiscWords * sizeof(uint32_t), s));
@@ -330,78 +333,101 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     a.ctr = o.counters ? as<unsigned long long>(c->ctr) : nullptr;
     a.err = misc;
 
-    // tier 0: every cell
-    a.tier = 0;
-    a.work_counter = misc + 16;
-    a.list = nullptr;
-    a.list_count = nullptr;
-    a.next_list = as<uint32_t>(c->lists[1]);
-    a.next_count = misc + 5;
-    a.stage = stage_of(c, 0);
-    c->tier_slots[0] = (int)n;
-    if (prof) VD_HIP(hipEventRecord(c->ev[1], s));
-    VD_HIP(vd::launch_clip(a, vd::clip_grid_workers(0, c->num_cu), nullptr, s));
-    if (prof) VD_HIP(hipEventRecord(c->ev[2], s));
+    // The clipping passes run back to back with no host synchronisation: the
+    // larger passes are launched with persistent grids that read their cell
+    // counts from device memory, on buffers sized beforehand for at least a
+    // floor of cells (n/64, n/4096 and 16 for the 256-, 1024- and
+    // 16384-vertex passes) and at least as many as earlier builds on this
+    // context needed.  A pass with more cells than slots leaves the extra ones
+    // undone and counts them; the one synchronisation at the end then sees the
+    // counts, the buffers grow, and the passes run again (a first build of a
+    // larger workload; the LBVH is kept).
     uint32_t hmisc[16];
-    VD_HIP(hipMemcpyAsync(hmisc, misc, sizeof(hmisc), hipMemcpyDeviceToHost, s));
-    VD_HIP(hipStreamSynchronize(s));
-    if (hmisc[0] & 1u) return fail(VD_ERR_INVALID_ARG, "vd_build: non-finite site coordinate or weight");
-    if (hmisc[0] & 2u) return fail(VD_ERR_INVALID_ARG, "vd_build: degenerate bounding box");
-    // larger tiers for the cells that outgrew the previous one
-    for (int tier = 1; tier < vd::kTiers; ++tier) c->tier_slots[tier] = 0;
-    for (int tier = 1; tier < vd::kTiers; ++tier) {
-        const uint32_t cnt = hmisc[4 + tier];
-        c->tier_slots[tier] = (int)cnt;
-        if (cnt == 0) break;
-        VD_TRY(ensure_stage(c, tier, cnt));
-        a.tier = tier;
-        a.work_counter = misc + 16 + vd::kWorkRanges * tier;
-        a.list = as<uint32_t>(c->lists[tier]);
-        a.list_count = misc + 4 + tier;
-        const bool last = tier + 1 == vd::kTiers;
-        a.next_list = last ? nullptr : as<uint32_t>(c->lists[tier + 1]);
-        a.next_count = last ? nullptr : misc + 5 + tier;
-        a.stage = stage_of(c, tier);
-        if (a.ctr) a.ctr = as<unsigned long long>(c->ctr) + tier * vd::kCtrCount;
-        // hand-over records: written by tier 2 for the first kHandoffMax
-        // cells it escalates, read by tier 3
-        if (tier == 2) {
-            const uint32_t cap = cnt < (uint32_t)vd::kHandoffMax ? cnt : (uint32_t)vd::kHandoffMax;
-            VD_TRY(ensure(c->handoff, (size_t)cap * sizeof(vd::Handoff)));
-            a.handoff = as<vd::Handoff>(c->handoff);
-            a.handoff_cap = cap;
-        } else if (tier != 3) {
-            a.handoff = nullptr;
-            a.handoff_cap = 0;
-        }
-        int workers = vd::clip_grid_workers(tier, c->num_cu);
-        if ((int64_t)workers > (int64_t)cnt) workers = (int)cnt;
-        void* arena = nullptr;
-        if (tier == 3) {
-            VD_TRY(ensure(c->arena, (size_t)workers * vd::arena_bytes_per_worker()));
-            arena = c->arena.p;
-        }
-        VD_HIP(vd::launch_clip(a, workers, arena, s));
-        if (prof && tier == 1) VD_HIP(hipEventRecord(c->ev[6], s));
-        VD_HIP(hipMemcpyAsync(hmisc, misc, sizeof(hmisc), hipMemcpyDeviceToHost, s));
-        VD_HIP(hipStreamSynchronize(s));
-    }
-    if (prof) {
-        VD_HIP(hipEventRecord(c->ev[3], s));
-        if (c->tier_slots[1] == 0) VD_HIP(hipEventRecord(c->ev[6], s));
-    }
-    VD_HIP(vd::scan_counts(as<uint32_t>(c->cnt_v), n, as<int64_t>(c->offv), as<int64_t>(c->scan_tmp), s));
-    VD_HIP(vd::scan_counts(as<uint32_t>(c->cnt_f), n, as<int64_t>(c->offf), as<int64_t>(c->scan_tmp), s));
-    VD_HIP(vd::scan_counts(as<uint32_t>(c->cnt_n), n, as<int64_t>(c->offn), as<int64_t>(c->scan_tmp), s));
     int64_t tot[3];
     unsigned long long st[vd::kStatCount];
-    VD_HIP(hipMemcpyAsync(&tot[0], as<int64_t>(c->offv) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    VD_HIP(hipMemcpyAsync(&tot[1], as<int64_t>(c->offf) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    VD_HIP(hipMemcpyAsync(&tot[2], as<int64_t>(c->offn) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    if (prof) VD_HIP(hipEventRecord(c->ev[4], s));
-    VD_HIP(hipMemcpyAsync(st, c->stats.p, sizeof(st), hipMemcpyDeviceToHost, s));
-    if (prof) VD_HIP(hipEventRecord(c->ev[5], s));
-    VD_HIP(hipStreamSynchronize(s));
+    for (int attempt = 0;; ++attempt) {
+        if (attempt > 0) {
+            VD_HIP(hipMemsetAsync(misc + 1, 0, (kMiscWords - 1) * sizeof(uint32_t), s));
+            VD_HIP(hipMemsetAsync(c->stats.p, 0, vd::kStatCount * sizeof(unsigned long long), s));
+            if (o.counters)
+                VD_HIP(hipMemsetAsync(c->ctr.p, 0, vd::kTiers * vd::kCtrCount * sizeof(unsigned long long), s));
+        }
+        uint32_t slots[vd::kTiers];
+        slots[0] = (uint32_t)n;
+        for (int t = 1; t < vd::kTiers; ++t) {
+            static constexpr uint32_t kDiv[vd::kTiers] = {1u, 64u, 4096u, 0u};
+            static constexpr uint32_t kFloor[vd::kTiers] = {0u, 1024u, 256u, 16u};
+            uint64_t cap = kDiv[t] ? (uint64_t)n / kDiv[t] : 0;
+            if (cap < kFloor[t]) cap = kFloor[t];
+            if (cap < c->seen[t]) cap = c->seen[t];
+            if (cap > (uint64_t)n) cap = (uint64_t)n;
+            slots[t] = (uint32_t)cap;
+            VD_TRY(ensure_stage(c, t, cap));
+        }
+        // hand-over records: every cell the 64-vertex pass may escalate, at
+        // most 8192 from the 256-vertex pass and 256 from the 1024-vertex pass
+        static constexpr uint32_t kHandMax[vd::kTiers - 1] = {0xFFFFFFFFu, 8192u, 256u};
+        uint32_t hand_cap[vd::kTiers - 1];
+        for (int t = 0; t + 1 < vd::kTiers; ++t) {
+            hand_cap[t] = slots[t + 1] < kHandMax[t] ? slots[t + 1] : kHandMax[t];
+            VD_TRY(ensure(c->hand[t], (size_t)hand_cap[t] * vd::handoff_bytes(t)));
+        }
+        // arena workers of the last pass: one per CU at most, as many as its
+        // cells of earlier builds at least 4 (they loop over the cells)
+        int arena_workers = (int)(c->seen[3] > 4u ? c->seen[3] : 4u);
+        if (arena_workers > c->num_cu) arena_workers = c->num_cu;
+        VD_TRY(ensure(c->arena, (size_t)arena_workers * vd::arena_bytes_per_worker()));
+
+        for (int tier = 0; tier < vd::kTiers; ++tier) {
+            const bool last = tier + 1 == vd::kTiers;
+            a.tier = tier;
+            a.work_counter = misc + 16 + vd::kWorkRanges * tier;
+            a.list = tier ? as<uint32_t>(c->lists[tier]) : nullptr;
+            a.list_count = tier ? misc + 4 + tier : nullptr;
+            a.slots = slots[tier];
+            a.deferred = misc + 1;
+            a.next_list = last ? nullptr : as<uint32_t>(c->lists[tier + 1]);
+            a.next_count = last ? nullptr : misc + 5 + tier;
+            a.stage = stage_of(c, tier);
+            a.ctr = o.counters ? as<unsigned long long>(c->ctr) + tier * vd::kCtrCount : nullptr;
+            a.hand_in = tier ? c->hand[tier - 1].p : nullptr;
+            a.hand_in_cap = tier ? hand_cap[tier - 1] : 0u;
+            a.hand_out = last ? nullptr : c->hand[tier].p;
+            a.hand_out_cap = last ? 0u : hand_cap[tier];
+            const int workers = last ? arena_workers : vd::clip_grid_workers(tier, c->num_cu);
+            if (prof && tier == 0) VD_HIP(hipEventRecord(c->ev[1], s));
+            VD_HIP(vd::launch_clip(a, workers, last ? c->arena.p : nullptr, s));
+            if (prof && tier == 0) VD_HIP(hipEventRecord(c->ev[2], s));
+            if (prof && tier == 1) VD_HIP(hipEventRecord(c->ev[6], s));
+        }
+        if (prof) VD_HIP(hipEventRecord(c->ev[3], s));
+        VD_HIP(vd::scan_counts(as<uint32_t>(c->cnt_v), n, as<int64_t>(c->offv), as<int64_t>(c->scan_tmp), s));
+        VD_HIP(vd::scan_counts(as<uint32_t>(c->cnt_f), n, as<int64_t>(c->offf), as<int64_t>(c->scan_tmp), s));
+        VD_HIP(vd::scan_counts(as<uint32_t>(c->cnt_n), n, as<int64_t>(c->offn), as<int64_t>(c->scan_tmp), s));
+        VD_HIP(hipMemcpyAsync(&tot[0], as<int64_t>(c->offv) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        VD_HIP(hipMemcpyAsync(&tot[1], as<int64_t>(c->offf) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        VD_HIP(hipMemcpyAsync(&tot[2], as<int64_t>(c->offn) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        if (prof) VD_HIP(hipEventRecord(c->ev[4], s));
+        VD_HIP(hipMemcpyAsync(st, c->stats.p, sizeof(st), hipMemcpyDeviceToHost, s));
+        VD_HIP(hipMemcpyAsync(hmisc, misc, sizeof(hmisc), hipMemcpyDeviceToHost, s));
+        if (prof) VD_HIP(hipEventRecord(c->ev[5], s));
+        VD_HIP(hipStreamSynchronize(s));  // the one synchronisation of a build
+        if (hmisc[0] & 1u) return fail(VD_ERR_INVALID_ARG, "vd_build: non-finite site coordinate or weight");
+        if (hmisc[0] & 2u) return fail(VD_ERR_INVALID_ARG, "vd_build: degenerate bounding box");
+        c->tier_slots[0] = (int)n;
+        bool short_before = false;
+        for (int t = 1; t < vd::kTiers; ++t) {
+            const uint32_t cnt = hmisc[4 + t];
+            c->tier_slots[t] = (int)cnt;
+            // behind a pass that left cells undone the counts are too low
+            const uint32_t want = short_before ? 2u * cnt + 16u : cnt;
+            if (want > c->seen[t]) c->seen[t] = want;
+            if (cnt > slots[t]) short_before = true;
+        }
+        if (hmisc[1] == 0) break;
+        if (attempt >= 2 * vd::kTiers)
+            return fail(VD_ERR_HIP, "vd_build: the larger passes kept outgrowing their buffers");
+    }
     c->profiled = prof;
     c->counted = o.counters != 0;
 

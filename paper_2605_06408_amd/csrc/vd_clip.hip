@@ -260,6 +260,10 @@ struct P64 {
 // holds the same copy of the cell-wide scalars (site, bounds, plane and
 // queue counts, flags) and changes it the same way, from values every wave
 // has seen.
+// Every member of Cell and the work loop are inlined into their kernel: as
+// calls (the inliner's size limits give up on the larger instantiations)
+// they cost a stack frame in scratch memory and spills around each call.
+#pragma clang attribute push(__attribute__((always_inline)), apply_to = function)
 template <int VPL, bool kLds, bool kCount, int G = 1, bool kSoS = false>
 struct Cell {
     static_assert(G == 1 || !Tier<VPL>::kReg, "wave groups need the vertex state in memory");
@@ -267,6 +271,14 @@ struct Cell {
     using W = typename T::W;
     static constexpr int CAP = T::CAP;
     static constexpr bool kReg = T::kReg;
+    // hand-over: every pass but the last writes the state of the cells it
+    // escalates; every pass but the first can take over such a state (from
+    // the pass of capacity kPrevCap)
+    static constexpr bool kSaves = CAP < kTierCap[kTiers - 1];
+    static constexpr int kPrevCap = CAP == kTierCap[1] ? kTierCap[0]
+                                    : (CAP == kTierCap[2] ? kTierCap[1] : (CAP == kTierCap[3] ? kTierCap[2] : 0));
+    static constexpr bool kResumes = kPrevCap > 0;
+    using HIn = HandoffT<(kPrevCap > 0 ? kPrevCap : 64)>;
     template <typename X>
     using Lane = Col<X, VPL, kReg, 64>;  // one value per slot of this lane
     template <typename X>
@@ -293,6 +305,12 @@ struct Cell {
     // squared far-corner coordinates, the directional and isotropic radii
     float blo0, blo1, blo2, bhi0, bhi1, bhi2;
     float hx2, hy2, hz2, lx2, ly2, lz2, rmax2, riso2;
+    // 64-vertex pass: the vertex at each side of the AABB (min x, y, z, max
+    // x, y, z) and the vertices the last effective clip removed; a clip that
+    // removes none of the six leaves the AABB as it was (new vertices lie on
+    // edges of the old cell)
+    uint32_t ext[6];
+    uint64_t cut_mask;
     // queue (entry q in lane q % 64, slot q / 64)
     Lane<uint32_t> qe;
     Lane<float> qk;
@@ -304,8 +322,9 @@ struct Cell {
     // where the last capacity overflow struck: in leaf ov_leaf, with the
     // candidates ov_mask still to try (ov_ok), else somewhere not resumable
     bool ov_ok;
-    uint32_t ov_leaf;
+    uint32_t ov_leaf, ov_phase, ov_skip;
     uint64_t ov_mask;
+    uint32_t leaf_phase = 1;  // 0 while clipping by the site's own leaf before any walk
     // work counters (uniform), accumulated over all cells of this wave
     uint64_t ctr[kCount ? kCtrCount : 1];
     static constexpr bool counting = kCount;
@@ -549,9 +568,47 @@ struct Cell {
         }
         blo0 = l0; blo1 = l1; blo2 = l2;
         bhi0 = h0; bhi1 = h1; bhi2 = h2;
-        hx2 = h0 * h0; hy2 = h1 * h1; hz2 = h2 * h2;
-        lx2 = l0 * l0; ly2 = l1 * l1; lz2 = l2 * l2;
+        if constexpr (VPL == 1 && G == 1) {
+            const bool al = (alive[0] >> ln) & 1;
+            ext[0] = lowest(ballot(al && y0[0] == l0));
+            ext[1] = lowest(ballot(al && y1[0] == l1));
+            ext[2] = lowest(ballot(al && y2[0] == l2));
+            ext[3] = lowest(ballot(al && y0[0] == h0));
+            ext[4] = lowest(ballot(al && y1[0] == h1));
+            ext[5] = lowest(ballot(al && y2[0] == h2));
+        }
+        derive_bounds();
+    }
+    __device__ __forceinline__ void derive_bounds() {
+        hx2 = bhi0 * bhi0; hy2 = bhi1 * bhi1; hz2 = bhi2 * bhi2;
+        lx2 = blo0 * blo0; ly2 = blo1 * blo1; lz2 = blo2 * blo2;
         rmax2 = fmaxf(hx2, lx2) + fmaxf(hy2, ly2) + fmaxf(hz2, lz2);
+    }
+    // After an effective clip: in the 64-vertex pass only the sides whose
+    // vertex the clip removed are reduced again.
+    __device__ void bounds_after_clip() {
+        if constexpr (VPL == 1 && G == 1) {
+            if (A.culling != 2) {
+                uint32_t lost = 0;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) lost |= (uint32_t)((cut_mask >> ext[k]) & 1ull) << k;
+                if (lost == 0) return;
+                const bool al = (alive[0] >> ln) & 1;
+#pragma unroll
+                for (int k = 0; k < 6; ++k) {
+                    if ((lost >> k) & 1u) {
+                        const float v = (k % 3 == 0) ? y0[0] : ((k % 3 == 1) ? y1[0] : y2[0]);
+                        const float m = k < 3 ? wmin(al ? v : INFINITY) : wmax(al ? v : -INFINITY);
+                        ext[k] = lowest(ballot(al && v == m));
+                        if (k == 0) blo0 = m; else if (k == 1) blo1 = m; else if (k == 2) blo2 = m;
+                        else if (k == 3) bhi0 = m; else if (k == 4) bhi1 = m; else bhi2 = m;
+                    }
+                }
+                derive_bounds();
+                return;
+            }
+        }
+        update_bounds();
     }
 
     // Squared radius of the cell toward direction a (far AABB corner of the
@@ -1158,11 +1215,13 @@ struct Cell {
         classify(ax, ay, az, b, sbh, hcode, hsite, robust == 0 ? 0 : (robust == 1 ? 1 : 3), R, &any, &all);
         bool ok;
         int r = apply(R, any, all, ax, ay, az, b, sbh, hcode, hsite, &ok);
+        if constexpr (VPL == 1 && G == 1) cut_mask = R[0];
         if (ok) return r;
         if (robust < 2) return kRestart;
         flags |= kFlagUncertain;
         classify(ax, ay, az, b, sbh, hcode, hsite, 2, R, &any, &all);
         r = apply(R, any, all, ax, ay, az, b, sbh, hcode, hsite, &ok);
+        if constexpr (VPL == 1 && G == 1) cut_mask = R[0];
         return ok ? r : kNone;
     }
 
@@ -1492,7 +1551,7 @@ struct Cell {
             return !(t > 0.f && t * t > a2 * r2);
         };
         uint64_t mask = ballot(keep(cand));
-        if constexpr (CAP > kHandoffCap) mask &= allow;
+        if constexpr (kResumes) mask &= allow;
         // from 256 vertices up, the candidates that miss the cell are dropped
         // all at once (not when every sign is taken in FP64)
         if constexpr (G > 1 || VPL == 4) {
@@ -1514,16 +1573,17 @@ struct Cell {
             const uint64_t t0 = tic();
             int r = clip(hx, hy, hz, hb, sb, (int32_t)(first + (uint32_t)L), hs);
             toc(kCtrCycClip, t0);
-            if constexpr (CAP == kHandoffCap) {
+            if constexpr (kSaves) {
                 if (r == kOverflow) {  // the cell is as before this candidate
                     ov_ok = true;
                     ov_leaf = ref;
                     ov_mask = mask | (1ull << L);
+                    ov_phase = leaf_phase;
                 }
             }
             if (r == kEmptied || r == kOverflow || r == kRestart) return r;
             if (r == kChanged) {
-                update_bounds();
+                bounds_after_clip();
                 mask &= ballot(keep(true));
             }
         }
@@ -1660,11 +1720,6 @@ struct Cell {
         const uint32_t oref = uni(A.nodes[rec >> 1].c[rec & 1].ref);
         *own = oref;
         *deep = false;
-        const uint64_t t0 = tic();
-        int r = leaf(oref, ~0ull);
-        toc(kCtrCycLeaf, t0);
-        if constexpr (CAP == kHandoffCap) ov_ok = false;  // no queue yet: a later pass starts over
-        if (r != kNone) return r;
         uint32_t e = rec ^ 1u;  // this lane's sibling record: (node << 1) | which child
         int ns = 1;
         for (uint32_t cur = rec;;) {
@@ -1685,6 +1740,12 @@ struct Cell {
         load_child(me >> 1, (int)(me & 1), &c);
         float key = 0.f, delta = 0.f;
         bool cull = true;
+        const uint64_t t0 = tic();
+        leaf_phase = 0;
+        int r = leaf(oref, ~0ull);
+        leaf_phase = 1;
+        toc(kCtrCycLeaf, t0);
+        if (r != kNone) return r;
         node_test(c, &key, &cull, &delta);
         uint64_t live = ballot(!cull && (int)ln < ns);
         while (live) {
@@ -1700,28 +1761,37 @@ struct Cell {
     // Alg. 1.  Returns kNone when done, kEmptied, kOverflow or kRestart.
     // A cell taken over from the previous pass (resume) first finishes the
     // leaf it stopped in, then goes on with the queue it brought.
-    __device__ int traverse(bool resume = false, uint32_t rleaf = 0, uint64_t rmask = 0) {
+    __device__ int traverse(bool resume = false, uint32_t rleaf = 0, uint64_t rmask = 0, uint32_t rphase = 1,
+                            uint32_t rskip = kNoParent) {
         uint32_t cur = A.root;
         bool have = true;
         uint64_t allow = ~0ull;  // candidates of the first leaf
-        if constexpr (CAP > kHandoffCap) {
+        if constexpr (kSaves) ov_ok = false;
+        uint32_t done_leaf = 0;
+        bool skip_done = false;
+        bool own_first = false;  // the first leaf is the site's own, then the walk starts at the root
+        if constexpr (kResumes) {
             if (resume) {
+                // the rest of the leaf it stopped in (one call site of leaf():
+                // through the loop below)
                 cur = rleaf;
                 allow = rmask;
+                own_first = rphase == 0;
+                if (rphase != 0 && rskip != kNoParent) {  // the own leaf, clipped before this walk
+                    done_leaf = rskip;
+                    skip_done = true;
+                }
             }
         }
-        if constexpr (CAP == kHandoffCap) ov_ok = false;
         // own leaf first, then the siblings of its path (not for a cell taken
         // over), in the 64-vertex pass only: for the cells that outgrew it
         // the walk from the root is faster (starting them at their own leaf
         // made the larger passes 40-60% slower on the power and surface
         // workloads)
-        uint32_t done_leaf = 0;
-        bool skip_done = false;
         if (!resume && A.leaf_of != nullptr) {
             if (A.warm_start > 0) {
                 const int rw = knn_warm(A.warm_start);
-                if constexpr (CAP == kHandoffCap) ov_ok = false;
+                if constexpr (kSaves) ov_ok = false;  // an overflow in the warm start starts over
                 if (rw != kNone) return rw;
             }
             if constexpr (VPL == 1) {
@@ -1779,10 +1849,22 @@ struct Cell {
             }
             if (have && !(skip_done && cur == done_leaf)) {
                 const uint64_t t0 = tic();
+                if constexpr (kResumes) leaf_phase = own_first ? 0u : 1u;
                 int r = leaf(cur, allow);
-                if constexpr (CAP > kHandoffCap) allow = ~0ull;
+                if constexpr (kResumes) leaf_phase = 1;
+                if constexpr (kSaves) ov_skip = skip_done ? done_leaf : kNoParent;
+                if constexpr (kResumes) allow = ~0ull;
                 toc(kCtrCycLeaf, t0);
                 if (r != kNone) return r;
+            }
+            if constexpr (kResumes) {
+                if (own_first) {  // the own leaf is done: from the root, passing over it
+                    own_first = false;
+                    done_leaf = cur;
+                    skip_done = true;
+                    cur = A.root;
+                    continue;
+                }
             }
             have = false;
             while (qn > 0) {
@@ -1815,10 +1897,10 @@ struct Cell {
     }
 
     // ------------------------------------------------------------ hand-over
-    // Writes the state of a cell that overflowed (1024-vertex pass) for the
-    // next pass; only the header when the overflow is not resumable.
-    __device__ void save(Handoff& H) {
-        if constexpr (!kReg && CAP == kHandoffCap) {
+    // Writes the state of a cell that overflowed for the next pass; only the
+    // header when the overflow is not resumable.
+    __device__ void save(HandoffT<(kSaves ? CAP : 64)>& H) {
+        if constexpr (kSaves) {
             sync();
             const int tid = (int)(wid * 64 + ln), step = 64 * G;
             if (ov_ok) {
@@ -1828,39 +1910,58 @@ struct Cell {
                     H.psb[q] = M.psb[q];
                     H.pcode[q] = M.pcode[q];
                 }
-                for (int q = tid; q < vhi; q += step) {
-                    H.y0[q] = M.y0[q];
-                    H.y1[q] = M.y1[q];
-                    H.y2[q] = M.y2[q];
-                    H.ev[q] = M.ev[q];
-                    H.vt[q] = M.vt[q];
-                    H.va[q] = M.va[q];
+                if constexpr (kReg) {
+#pragma unroll
+                    for (int s = 0; s < VPL; ++s) {
+                        const int q = s * 64 + (int)ln;
+                        H.y0[q] = y0[s];
+                        H.y1[q] = y1[s];
+                        H.y2[q] = y2[s];
+                        H.ev[q] = ev[s];
+                        H.vt[q] = vt[s];
+                        H.va[q] = va[s];
+                        H.qe[q] = qe[s];
+                        H.qk[q] = qk[s];
+                        if (ln == 0) H.alive[s] = alive[s];
+                    }
+                } else {
+                    for (int q = tid; q < vhi; q += step) {
+                        H.y0[q] = M.y0[q];
+                        H.y1[q] = M.y1[q];
+                        H.y2[q] = M.y2[q];
+                        H.ev[q] = M.ev[q];
+                        H.vt[q] = M.vt[q];
+                        H.va[q] = M.va[q];
+                    }
+                    for (int q = tid; q < qn; q += step) {
+                        H.qe[q] = M.qe[q];
+                        H.qk[q] = M.qk[q];
+                    }
+                    if (tid < nsv()) H.alive[tid] = M.alive[tid];
                 }
-                for (int q = tid; q < qn; q += step) {
-                    H.qe[q] = M.qe[q];
-                    H.qk[q] = M.qk[q];
-                }
-                if (tid < nsv()) H.alive[tid] = M.alive[tid];
             }
             if (tid < kMaxWarm) H.wsite[tid] = tid < nwarm ? wsite : 0u;  // lane t of wave 0 holds site t
             if (tid == 0) {
                 H.nwarm = (uint32_t)nwarm;
                 H.np = (uint32_t)np;
-                H.vhi = (uint32_t)vhi;
+                H.vhi = (uint32_t)(kReg ? CAP : vhi);
                 H.qn = (uint32_t)qn;
                 H.flags = flags;
                 H.robust = (uint32_t)robust;
                 H.leaf = ov_leaf;
                 H.mask = ov_mask;
+                H.phase = ov_phase;
+                H.skip = ov_phase == 0 ? kNoParent : ov_skip;
                 H.valid = ov_ok ? 1u : 0u;
             }
         }
     }
 
-    // Takes over a cell saved by the 1024-vertex pass (instead of init):
-    // the traversal then goes on with resume = true, H.leaf, H.mask.
-    __device__ void resume(uint32_t k, const Handoff& H) {
-        if constexpr (!kReg && CAP > kHandoffCap) {
+    // Takes over a cell saved by the previous pass (instead of init): the
+    // traversal then goes on with resume = true, H.leaf, H.mask, H.phase.
+    // Vertex, plane and queue numbers are the same in every pass.
+    __device__ void resume(uint32_t k, const HIn& H) {
+        if constexpr (kResumes) {
             sync();  // every wave is done with the previous cell
             self = k;
             float4 s = A.pts[k];
@@ -1879,21 +1980,46 @@ struct Cell {
                 M.psb[q] = H.psb[q];
                 M.pcode[q] = H.pcode[q];
             }
-            // vertex and plane indices: ten bits each there, wider here
-            auto wide = [](uint32_t x) { return T::pack3(x & 1023u, (x >> 10) & 1023u, (x >> 20) & 1023u); };
-            for (int q = tid; q < vhi; q += step) {
-                M.y0[q] = H.y0[q];
-                M.y1[q] = H.y1[q];
-                M.y2[q] = H.y2[q];
-                M.ev[q] = H.ev[q];
-                M.vt[q] = wide(H.vt[q]);
-                M.va[q] = wide(H.va[q]);
+            if constexpr (kReg) {
+#pragma unroll
+                for (int s2 = 0; s2 < VPL; ++s2) {
+                    const int q = s2 * 64 + (int)ln;
+                    if (s2 < kPrevCap / 64) {
+                        y0[s2] = H.y0[q];
+                        y1[s2] = H.y1[q];
+                        y2[s2] = H.y2[q];
+                        ev[s2] = H.ev[q];
+                        vt[s2] = H.vt[q];
+                        va[s2] = H.va[q];
+                        qe[s2] = H.qe[q];
+                        qk[s2] = H.qk[q];
+                        alive[s2] = H.alive[s2];
+                    } else {
+                        alive[s2] = 0ull;
+                    }
+                }
+                vhi = CAP;
+            } else {
+                // vertex and plane indices: ten bits each there, wider here
+                // above 1024 vertices
+                auto wide = [](uint32_t x) -> W {
+                    if constexpr (T::kNarrow) return (W)x;
+                    else return T::pack3(x & 1023u, (x >> 10) & 1023u, (x >> 20) & 1023u);
+                };
+                for (int q = tid; q < vhi; q += step) {
+                    M.y0[q] = H.y0[q];
+                    M.y1[q] = H.y1[q];
+                    M.y2[q] = H.y2[q];
+                    M.ev[q] = H.ev[q];
+                    M.vt[q] = wide(H.vt[q]);
+                    M.va[q] = wide(H.va[q]);
+                }
+                for (int q = tid; q < qn; q += step) {
+                    M.qe[q] = H.qe[q];
+                    M.qk[q] = H.qk[q];
+                }
+                if (tid < nsv()) M.alive[tid] = H.alive[tid];
             }
-            for (int q = tid; q < qn; q += step) {
-                M.qe[q] = H.qe[q];
-                M.qk[q] = H.qk[q];
-            }
-            if (tid < nsv()) M.alive[tid] = H.alive[tid];
             sync();
             update_bounds();
         }
@@ -2131,8 +2257,9 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
     // the input checks (non-finite values, a flat box) ran before this pass:
     // on such input no cell is built
     if (*ka->err != 0u) return;
-    Cell<VPL, kLds, kCount, G, kSoS> C(M, A, gx);
     const uint32_t count = ka->list ? *ka->list_count : (uint32_t)A.n;
+    if (count == 0) return;  // a larger pass with no cell
+    Cell<VPL, kLds, kCount, G, kSoS> C(M, A, gx);
     unsigned long long st_empty = 0, st_large = 0, st_unc = 0, st_fail = 0, st_fp64 = 0, st_res = 0, st_pert = 0;
     // Cells are split into kWorkRanges contiguous (Morton-ordered) ranges, one
     // per XCD: the waves of workgroup b take chunks of their own range b % 8
@@ -2166,13 +2293,24 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
         }
         const uint32_t c = cur++;
         KArgs* kc = cold_args();
+        if (kc->list && c >= kc->slots) {
+            // no staging slot: left undone and counted (the build runs the
+            // passes again with more slots)
+            if (C.ln == 0 && C.lead()) atomicAdd(kc->deferred, 1u);
+            continue;
+        }
         const uint32_t k = kc->list ? kc->list[c] : c;
         const uint32_t slot = kc->list ? c : k;
         const uint32_t orig = kc->order[k];
         // a cell the previous pass handed over goes on from where it stopped
-        const Handoff* hin = nullptr;
-        if constexpr (Tier<VPL>::CAP > kHandoffCap)
-            if (kc->handoff && c < kc->handoff_cap && kc->handoff[c].valid) hin = &kc->handoff[c];
+        using CellT = Cell<VPL, kLds, kCount, G, kSoS>;
+        const typename CellT::HIn* hin = nullptr;
+        if constexpr (CellT::kResumes) {
+            if (kc->hand_in && c < kc->hand_in_cap) {
+                const auto* h = static_cast<const typename CellT::HIn*>(kc->hand_in) + c;
+                if (h->valid) hin = h;
+            }
+        }
         // a cell is built with plain FP32 signs first (mixed mode: with FP64
         // re-evaluation of doubtful ones); if that meets an inconsistent
         // configuration it is rebuilt with the FP64 re-evaluation, then with
@@ -2191,7 +2329,8 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
             if (attempt > 0) C.flags |= kFlagFP64;
             if (A.tier > 0) C.flags |= kFlagLarge;
             const uint64_t t0 = C.tic();
-            int r = C.traverse(res, res ? hin->leaf : 0u, res ? hin->mask : 0ull);
+            int r = C.traverse(res, res ? hin->leaf : 0u, res ? hin->mask : 0ull, res ? hin->phase : 1u,
+                               res ? hin->skip : kNoParent);
             C.toc(kCtrCycTraverse, t0);
             if (r == kRestart) {
                 C.robust = C.robust + 1;
@@ -2205,9 +2344,10 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
                         pos = atomicAdd(kn->next_count, 1u);
                         kn->next_list[pos] = k;
                     }
-                    if constexpr (Tier<VPL>::CAP == kHandoffCap) {
+                    if constexpr (CellT::kSaves) {
                         pos = C.bcast(pos);
-                        if (kn->handoff && pos < kn->handoff_cap) C.save(kn->handoff[pos]);
+                        if (kn->hand_out && pos < kn->hand_out_cap)
+                            C.save(static_cast<HandoffT<CellT::CAP>*>(kn->hand_out)[pos]);
                     }
                     escalated = true;
                 } else {
@@ -2267,6 +2407,8 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
     }
 }
 
+#pragma clang attribute pop
+
 // Register tiers: per-cell arrays in LDS, WAVES independent waves per
 // block.  Register budgets: the 64-vertex pass is held to 128 registers for
 // 4 waves per SIMD, the 256-vertex pass to 256 for 2 (a few spills cost less
@@ -2309,6 +2451,15 @@ static_assert(Tier<kArenaVPL>::CAP <= (1 << Tier<kArenaVPL>::kB) && Tier<kArenaV
 }  // namespace
 
 size_t arena_bytes_per_worker() { return sizeof(WaveMem<kArenaVPL>); }
+
+size_t handoff_bytes(int tier) {
+    switch (tier) {
+        case 0: return sizeof(HandoffT<kTierCap[0]>);
+        case 1: return sizeof(HandoffT<kTierCap[1]>);
+        case 2: return sizeof(HandoffT<kTierCap[2]>);
+        default: return 0;
+    }
+}
 
 int clip_grid_workers(int tier, int num_cu) {
     int per_cu = 0;

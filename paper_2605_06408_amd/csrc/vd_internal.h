@@ -81,30 +81,36 @@ enum StatIndex { kStatEmpty = 0, kStatLarge, kStatUncertain, kStatFailed, kStatF
 enum CtrIndex { kCtrClassify = 0, kCtrNewVertex, kCtrNode, kCtrSite, kCtrFinal, kCtrClip, kCtrEffective, kCtrLeaf,
                 kCtrBall, kCtrFP64, kCtrCycTraverse, kCtrCycLeaf, kCtrCycClip, kCtrCycFinal, kCtrCount };
 
-// State of a cell that outgrew the 1024-vertex pass while clipping by the
-// sites of a leaf, handed to the 16384-vertex pass so that the cell goes on
-// from there instead of starting over: vertices (same numbering, indices
-// packed ten bits each as in the 1024-vertex pass), planes, node queue, and
-// the leaf with its candidates not yet tried.
+// State of a cell that outgrew a clipping pass while clipping by the sites
+// of a leaf, handed to the next pass so that the cell goes on from there
+// instead of starting over: vertices (same numbering; indices packed ten bits
+// each, as in every pass up to 1024 vertices), planes, node queue, and the
+// leaf with its candidates not yet tried.  phase 0: the leaf was the site's
+// own leaf, clipped before any walk (the next pass finishes it, then walks
+// from the root passing over it); 1: a leaf of the walk (the next pass
+// finishes it, then goes on with the queue).  HC: capacity of the pass that
+// writes the record.
 constexpr int kMaxWarm = 16;       // largest K of the KNN warm start
-constexpr int kHandoffCap = 1024;   // vertices, planes and queue entries (kTierCap[2])
-constexpr int kHandoffMax = 256;    // cells handed over per build (later ones start over)
-struct Handoff {
-    float4 pl[kHandoffCap];       // planes: a.xyz, b
-    float4 psite[kHandoffCap];    // the plane's site
-    unsigned long long alive[kHandoffCap / 64];
-    unsigned long long mask;      // candidates of the leaf still to try (lanes)
-    float y0[kHandoffCap], y1[kHandoffCap], y2[kHandoffCap], ev[kHandoffCap];
-    uint32_t vt[kHandoffCap], va[kHandoffCap];
-    float psb[kHandoffCap];
-    int32_t pcode[kHandoffCap];
-    uint32_t qe[kHandoffCap];
-    float qk[kHandoffCap];
-    uint32_t valid;               // 1: the state above can be resumed
-    uint32_t np, vhi, qn, flags, robust, leaf;
-    uint32_t nwarm;               // sites of the KNN warm start (passed over by the leaves)
+template <int HC>
+struct HandoffT {
+    float4 pl[HC];            // planes: a.xyz, b
+    float4 psite[HC];         // the plane's site
+    unsigned long long alive[HC / 64];
+    unsigned long long mask;  // candidates of the leaf still to try (lanes)
+    float y0[HC], y1[HC], y2[HC], ev[HC];
+    uint32_t vt[HC], va[HC];
+    float psb[HC];
+    int32_t pcode[HC];
+    uint32_t qe[HC];
+    float qk[HC];
+    uint32_t valid;           // 1: the state above can be resumed
+    uint32_t np, vhi, qn, flags, robust, leaf, phase;
+    uint32_t skip;            // a leaf the walk must pass over (already clipped), or kNoParent
+    uint32_t nwarm;           // sites of the KNN warm start (passed over by the leaves)
     uint32_t wsite[kMaxWarm];
 };
+// Bytes of the hand-over record that the pass of tier t writes (t < kTiers - 1).
+size_t handoff_bytes(int tier);
 
 struct ClipArgs {
     const float4* pts;        // sites in Morton order: x, y, z, w (w = -inf: coincident loser)
@@ -128,12 +134,19 @@ struct ClipArgs {
     uint32_t* work_counter;
     const uint32_t* list;
     const uint32_t* list_count;   // device count (list != null), else count = n
+    uint32_t slots;           // staging slots of this pass (list tiers: cells at
+                              // list positions from slots on are left undone)
+    uint32_t* deferred;       // counts the cells left undone
     uint32_t* next_list;      // escalation list for the next tier (null: last tier)
     uint32_t* next_count;
-    // tier 2 writes, tier 3 reads the hand-over of escalated cell c (list
-    // position) for c < handoff_cap; null elsewhere
-    Handoff* handoff;
-    uint32_t handoff_cap;
+    // hand-over records (HandoffT of this pass's capacity) written for the
+    // cells this pass escalates, at their position in next_list, for
+    // positions below hand_out_cap (null: none); and those the previous pass
+    // wrote, read for the cells of this pass's list below hand_in_cap
+    void* hand_out;
+    uint32_t hand_out_cap;
+    const void* hand_in;
+    uint32_t hand_in_cap;
     Stage stage;
     uint32_t* loc;            // [n] by Morton position
     uint32_t* cnt_v;          // [n] by original index

@@ -261,8 +261,9 @@ def test_very_large_cells(oracle_mod, kind, precision):
     d = gpu_build(xyz, w, box, precision=precision)
     assert d.sizes["n_failed"] == 0
     assert d.sizes["n_huge"] >= 1
-    # cells that outgrew 1024 vertices mid-leaf go on from that state
-    assert 1 <= d.sizes["n_resumed"] <= d.sizes["n_huge"]
+    # cells that outgrew a pass mid-leaf go on from that state in the next
+    # (a cell can be taken over once by each pass above the first)
+    assert 1 <= d.sizes["n_resumed"] <= 3 * d.sizes["n_large"]
     g_all = to_numpy(d)
     assert g_all["vol"].astype(np.float64).sum() == pytest.approx(1.0, rel=1e-5)
     rng = np.random.default_rng(5)
@@ -288,6 +289,52 @@ def test_very_large_cells(oracle_mod, kind, precision):
 
 
 # ------------------------------------------------------------ errors
+
+def _hedgehogs(m, per, seed):
+    """m centres on a jittered grid, each ringed by `per` sites on a small
+    sphere around it (randomly rotated): every centre's cell has `per`
+    facets, so 2 per - 4 vertices, above the 64 of the first pass."""
+    rng = np.random.default_rng(seed)
+    g = int(np.ceil(m ** (1.0 / 3.0)))
+    idx = np.array([(a, b, c) for a in range(g) for b in range(g) for c in range(g)][:m], np.float64)
+    h = 1.0 / g
+    centres = (idx + 0.5 + rng.uniform(-0.1, 0.1, idx.shape)) * h
+    k = np.arange(per) + 0.5
+    phi = np.arccos(1.0 - 2.0 * k / per)
+    th = np.pi * (1.0 + 5.0 ** 0.5) * k
+    shell = np.stack([np.cos(th) * np.sin(phi), np.sin(th) * np.sin(phi), np.cos(phi)], axis=1)
+    pts = [centres]
+    for c in centres:
+        q, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+        pts.append(c + 0.25 * h * shell @ q.T)
+    return np.concatenate(pts).astype(np.float32), np.array([0.0, 0.0, 0.0, 1.0, 1.0, 1.0])
+
+
+def test_more_large_cells_than_the_first_slots(oracle_mod):
+    """A fresh context stages at most max(1024, n/64) cells of the 256-vertex
+    pass; 1100 centres each needing that pass exceed it, so the first build
+    leaves cells undone, grows its buffers and runs the passes again.  The
+    result must match the oracle and a second build (no retry) exactly."""
+    import torch
+    import paper_2605_06408_amd as vd
+    xyz, box = _hedgehogs(1100, 40, 31)
+    n = len(xyz)
+    ctx = vd.Context(0)
+    x = torch.from_numpy(xyz).cuda()
+    D1 = ctx.build(x, None, bbox=[float(v) for v in box])
+    s1 = dict(ctx.last_sizes)
+    assert s1["n_large"] >= 1100 > max(1024, n // 64)
+    assert s1["n_failed"] == 0
+    d1 = to_numpy(D1)
+    d2 = to_numpy(ctx.build(x, None, bbox=[float(v) for v in box]))
+    for k in d1:
+        assert np.array_equal(d1[k], d2[k]), k
+    ids = np.unique(np.concatenate([np.arange(200), np.random.default_rng(3).choice(n, 800, replace=False)]))
+    o = oracle_mod.cells(xyz, None, box, ids=ids)
+    rep = compare(to_numpy(D1, ids), o)
+    assert_parity(rep, 0.8)
+    ctx.close()
+
 
 def test_non_finite_input_rejected():
     import paper_2605_06408_amd as vd
