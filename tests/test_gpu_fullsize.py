@@ -15,16 +15,30 @@ pytestmark = pytest.mark.gpu
 
 def _sample(d, n, rng, k_random, k_large, k_empty):
     """Random cells, cells of the larger-capacity passes (all of them up to
-    k_large) and empty cells; the oracle's k-d tree mode makes each cheap."""
+    k_large) and empty cells; the oracle's k-d tree mode makes each cheap.
+    Returns the ids, the count of larger-pass cells and the random draw."""
     flags = d.flags.cpu().numpy()
-    ids = set(rng.choice(n, min(n, k_random), replace=False).tolist())
+    rand = rng.choice(n, min(n, k_random), replace=False)
+    ids = set(rand.tolist())
     large = np.nonzero(flags & 4)[0]
     if len(large):
         ids |= set(rng.choice(large, min(len(large), k_large), replace=False).tolist())
     empty = np.nonzero(flags & 1)[0]
     if len(empty):
         ids |= set(rng.choice(empty, min(len(empty), k_empty), replace=False).tolist())
-    return np.array(sorted(ids), np.int64), len(large)
+    return np.array(sorted(ids), np.int64), len(large), rand
+
+
+def _check(rep, ids, rand, o, tau=1e-5):
+    """Certified cells must match (topology and geometry); the random draw,
+    which stands for the workload, must be at least 90% certified (the cells
+    of the larger passes, many planes each, are often within rounding of a
+    degeneracy and are held only to matching where certified)."""
+    assert_parity(rep, 0.0)
+    row = {int(i): t for t, i in enumerate(ids)}
+    cert = np.array([o["margin"][row[int(i)]] >= tau for i in rand])
+    print("random draw: %d of %d certified" % (int(cert.sum()), len(cert)))
+    assert cert.mean() >= 0.9
 
 
 def _invariants(oracle_mod, d, xyz, w, box, tau=1e-5):
@@ -59,15 +73,15 @@ def test_one_million(oracle_mod, name, seed):
     xyz, w, box = wl.make(name, seed)
     d = gpu_build(xyz, w, box)
     _invariants(oracle_mod, d, xyz, w, box)
-    ids, n_large = _sample(d, len(xyz), np.random.default_rng(1 + seed), k_random=20000, k_large=20000,
-                           k_empty=500)
+    ids, n_large, rand = _sample(d, len(xyz), np.random.default_rng(1 + seed), k_random=20000, k_large=20000,
+                                 k_empty=500)
     g = to_numpy(d, ids)
     o = oracle_mod.cells(xyz, w, box, ids=ids)
     rep = compare(g, o)
     rep["sizes"] = d.sizes
     print("%s seed %d: %d cells compared (%d of the larger passes, of %d)"
           % (name, seed, len(ids), int(((g["flags"] & 4) != 0).sum()), n_large))
-    assert_parity(rep, 0.8)
+    _check(rep, ids, rand, o)
 
 
 @pytest.mark.parametrize("seed", [0, 1, 2])
@@ -75,11 +89,11 @@ def test_surface_twenty_million(oracle_mod, seed):
     xyz, w, box = wl.make("surface_20m", seed)
     d = gpu_build(xyz, w, box)
     _invariants(oracle_mod, d, xyz, w, box)
-    ids, n_large = _sample(d, len(xyz), np.random.default_rng(2 + seed), k_random=5000, k_large=5000, k_empty=0)
+    ids, n_large, rand = _sample(d, len(xyz), np.random.default_rng(2 + seed), k_random=5000, k_large=5000, k_empty=0)
     g = to_numpy(d, ids)
     o = oracle_mod.cells(xyz, w, box, ids=ids)
     rep = compare(g, o)
     rep["sizes"] = d.sizes
     print("surface_20m seed %d: %d cells compared (%d of the larger passes, of %d)"
           % (seed, len(ids), int(((g["flags"] & 4) != 0).sum()), n_large))
-    assert_parity(rep, 0.8)
+    _check(rep, ids, rand, o)
