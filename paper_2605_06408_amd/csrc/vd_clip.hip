@@ -820,7 +820,8 @@ struct Cell {
     __device__ static double xdot(const double* u, const double* v, bool& ok) {
         return xadd(xadd(xmul(u[0], v[0], ok), xmul(u[1], v[1], ok), ok), xmul(u[2], v[2], ok), ok);
     }
-    __device__ int side_exact(W t, int32_t hcode, float4 hsite) const {
+    __device__ int side_exact(W t, int32_t hcode) const {
+        const float4 hsite = A.pts[hcode];
         bool ok = true;
         const PX P0 = plane_exact(M.pcode[T::fld(t, 0)], M.psite[T::fld(t, 0)], ok);
         const PX P1 = plane_exact(M.pcode[T::fld(t, 1)], M.psite[T::fld(t, 1)], ok);
@@ -860,7 +861,7 @@ struct Cell {
     // ------------------------------------------------------------ clip
     // mode 0: plain FP32 signs; 1: doubtful signs re-evaluated in FP64;
     // 2: doubtful signs taken as inside; 3: every sign evaluated in FP64.
-    __device__ void classify(float ax, float ay, float az, float b, float sbh, int32_t hcode, float4 hsite,
+    __device__ void classify(float ax, float ay, float az, float b, float sbh, int32_t hcode,
                              int mode, Wave<uint64_t>& R, bool* any_out, bool* all_out) {
         const float an1 = fabsf(ax) + fabsf(ay) + fabsf(az);
         if (kCount && mode != 2) count(kCtrClassify, nalive());
@@ -923,7 +924,7 @@ struct Cell {
                 for (int s = 0; s < (kReg ? VPL : ns); ++s) na += (uint64_t)popc(ballot(amb[s] != 0));
                 count(kCtrFP64, na);
             }
-            P64 h = plane64(hcode, hsite);
+            P64 h = plane64(hcode, A.pts[hcode]);
             anyo = false;
             allo = true;
             bool uns = false, pert = false;
@@ -935,7 +936,7 @@ struct Cell {
                     int sg = side64(vt[s], h);
                     if constexpr (kSoS) {
                         if (sg == 0) {
-                            sg = side_exact(vt[s], hcode, hsite);
+                            sg = side_exact(vt[s], hcode);
                             tie = sg == 2 || sg == -2;
                         }
                     }
@@ -974,7 +975,7 @@ struct Cell {
     // Tries the clip with the given outside masks; on an inconsistent
     // boundary sets *consistent = false and leaves the cell untouched.
     __device__ int apply(Wave<uint64_t>& R, bool any, bool all, float ax, float ay, float az, float b, float sbh,
-                         int32_t hcode, float4 hsite, bool* consistent) {
+                         int32_t hcode, bool* consistent) {
         *consistent = true;
         const int ns = nsv();
         if (!any) return kNone;
@@ -1194,7 +1195,7 @@ struct Cell {
             M.pl[h] = make_float4(ax, ay, az, b);
             M.psb[h] = sbh;
             M.pcode[h] = hcode;
-            M.psite[h] = hsite;
+            M.psite[h] = A.pts[hcode];
         }
         np = (int)h + 1;
         sync();
@@ -1207,20 +1208,20 @@ struct Cell {
     // inconsistent boundary in FP32 asks for that rebuild; in the robust modes
     // doubtful signs fall back to "inside" and, failing that, the plane is
     // skipped and the cell flagged.
-    __device__ int clip(float ax, float ay, float az, float b, float sbh, int32_t hcode, float4 hsite) {
+    __device__ int clip(float ax, float ay, float az, float b, float sbh, int32_t hcode) {
         Wave<uint64_t> R;
         if constexpr (!kReg) R.m = M.R;
         count(kCtrClip, 1);
         bool any, all;
-        classify(ax, ay, az, b, sbh, hcode, hsite, robust == 0 ? 0 : (robust == 1 ? 1 : 3), R, &any, &all);
+        classify(ax, ay, az, b, sbh, hcode, robust == 0 ? 0 : (robust == 1 ? 1 : 3), R, &any, &all);
         bool ok;
-        int r = apply(R, any, all, ax, ay, az, b, sbh, hcode, hsite, &ok);
+        int r = apply(R, any, all, ax, ay, az, b, sbh, hcode, &ok);
         if constexpr (VPL == 1 && G == 1) cut_mask = R[0];
         if (ok) return r;
         if (robust < 2) return kRestart;
         flags |= kFlagUncertain;
-        classify(ax, ay, az, b, sbh, hcode, hsite, 2, R, &any, &all);
-        r = apply(R, any, all, ax, ay, az, b, sbh, hcode, hsite, &ok);
+        classify(ax, ay, az, b, sbh, hcode, 2, R, &any, &all);
+        r = apply(R, any, all, ax, ay, az, b, sbh, hcode, &ok);
         if constexpr (VPL == 1 && G == 1) cut_mask = R[0];
         return ok ? r : kNone;
     }
@@ -1537,6 +1538,7 @@ struct Cell {
             for (int t = 0; t < nwarm; ++t) cand = cand && j != rdl(wsite, t);
             key = cand ? b * __builtin_amdgcn_rsqf(a2) : INFINITY;  // orders candidates only
         }
+        const float sbl = 0.5f * (a2 + fabsf(dw));  // size of the terms of b (error scale)
         auto keep = [&](bool c) -> bool {
             if (!c) return false;
             if (A.culling == 3) {
@@ -1568,10 +1570,9 @@ struct Cell {
             }
             mask &= ~(1ull << L);
             float hx = rdl(ax, L), hy = rdl(ay, L), hz = rdl(az, L), hb = rdl(b, L);
-            float sb = 0.5f * (rdl(a2, L) + fabsf(rdl(dw, L)));
-            float4 hs = make_float4(rdl(q.x, L), rdl(q.y, L), rdl(q.z, L), rdl(q.w, L));
+            const float sb = rdl(sbl, L);
             const uint64_t t0 = tic();
-            int r = clip(hx, hy, hz, hb, sb, (int32_t)(first + (uint32_t)L), hs);
+            int r = clip(hx, hy, hz, hb, sb, (int32_t)(first + (uint32_t)L));
             toc(kCtrCycClip, t0);
             if constexpr (kSaves) {
                 if (r == kOverflow) {  // the cell is as before this candidate
@@ -1694,7 +1695,7 @@ struct Cell {
             const float a2 = fmaf(ax, ax, fmaf(ay, ay, az * az));
             const float dw = pw - q.w;
             const uint64_t t0 = tic();
-            const int r = clip(ax, ay, az, 0.5f * (a2 + dw), 0.5f * (a2 + fabsf(dw)), (int32_t)j, q);
+            const int r = clip(ax, ay, az, 0.5f * (a2 + dw), 0.5f * (a2 + fabsf(dw)), (int32_t)j);
             toc(kCtrCycClip, t0);
             if (r == kEmptied || r == kOverflow || r == kRestart) return r;
             if (r == kChanged) update_bounds();
