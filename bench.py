@@ -54,9 +54,10 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 # workload, each scaled by what the same counter reads for a plain 256 MiB
 # device copy in the same run.  Valid only while the kernel source is unchanged.
 TRAFFIC_MEASURED = {
-    "sources_sha1": {"paper_2605_06408_amd/csrc/vd_clip.hip": "",
-                     "paper_2605_06408_amd/csrc/vd_internal.h": ""},
-    "workload": "clustered_1m", "fetch_kib": 0.0, "write_kib": 0.0, "fetch_scale": 2.0, "write_scale": 1.0,
+    "sources_sha1": {"paper_2605_06408_amd/csrc/vd_clip.hip": "203c522249632552571ca8577977e4e425afc4f6",
+                     "paper_2605_06408_amd/csrc/vd_internal.h": "f0bbf7e0269414dad7b4d7d51d914898968ff007"},
+    "workload": "clustered_1m", "fetch_kib": 56305.6875, "write_kib": 1101938.8125, "fetch_scale": 2.0,
+    "write_scale": 1.0,
 }
 
 
