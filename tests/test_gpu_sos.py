@@ -111,3 +111,50 @@ def test_perturbation_changes_nothing_in_general_position(kind):
     for k in ("nbr_off", "nbr", "facet_off", "facet_nbr", "fv_off", "fv", "vert_off", "vert", "vert_planes", "vol",
               "centroid"):
         assert np.array_equal(a[k], b[k]), k
+
+
+def test_perturbed_lattice_at_size():
+    """A 16^3 dyadic lattice (4096 sites, every diagram vertex shared by eight
+    cells) built with the perturbation: properties that hold at any size.
+    Every cell is the cube of side h about its site (zero-area facets add
+    nothing), the perturbed cells are simple polytopes (F = V/2 + 2) with
+    symmetric neighbours, and the dual tetrahedra tile the lattice's hull
+    exactly once: their absolute volumes (exact in FP64 for these
+    coordinates) sum to the hull's, and every triangle is shared by two
+    tetrahedra or lies on the hull."""
+    import itertools
+    import torch
+    import paper_2605_06408_amd as vd
+    m, h = 16, 1.0 / 16
+    xyz = lattice(m, h, h / 2)
+    box = np.array([0.0, 0.0, 0.0, 1.0, 1.0, 1.0])
+    ctx = vd.Context(0)
+    d = ctx.build(torch.from_numpy(xyz).cuda(), None, bbox=[float(v) for v in box], perturb=1)
+    tets = ctx.tetrahedra().cpu().numpy().astype(np.int64)
+    torch.cuda.synchronize()
+    g = to_numpy(d)
+    n = len(xyz)
+    assert d.sizes["n_uncertain"] == 0 and d.sizes["n_failed"] == 0 and d.sizes["n_perturbed"] > 0
+    assert np.abs(g["vol"].astype(np.float64) / h ** 3 - 1.0).max() <= 1e-6
+    assert np.abs(g["centroid"].astype(np.float64) - xyz).max() <= 1e-6
+    nv = np.diff(g["vert_off"])
+    nf = np.diff(g["facet_off"])
+    assert np.all(nf == nv // 2 + 2)
+    rows = np.repeat(np.arange(n), np.diff(g["nbr_off"]))
+    pairs = set(zip(rows.tolist(), g["nbr"].tolist()))
+    assert all((j, i) in pairs for i, j in pairs)
+    P = xyz.astype(np.float64)
+    a, b, c, e = (P[tets[:, k]] for k in range(4))
+    vol = np.abs(np.einsum("ij,ij->i", b - a, np.cross(c - a, e - a))) / 6.0
+    lo, hi = h / 2, 1.0 - h / 2
+    assert vol.sum() == pytest.approx((hi - lo) ** 3, rel=1e-12)
+    faces = {}
+    for t in tets.tolist():
+        for f in itertools.combinations(t, 3):
+            faces[f] = faces.get(f, 0) + 1
+    assert set(faces.values()) <= {1, 2}
+    for f, cnt in faces.items():
+        if cnt == 1:
+            q = P[list(f)]
+            assert any(np.all(q[:, ax] == s) for ax in range(3) for s in (lo, hi)), f
+    ctx.close()
