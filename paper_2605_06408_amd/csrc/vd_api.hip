@@ -322,6 +322,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     a.warm_start = o.warm_start;
     a.precision = o.precision;
     a.perturb = o.perturb;
+    a.weighted = w != nullptr ? 1 : 0;
     a.loc = as<uint32_t>(c->loc);
     a.cnt_v = as<uint32_t>(c->cnt_v);
     a.cnt_f = as<uint32_t>(c->cnt_f);

@@ -41,6 +41,11 @@
 
 #include "vd_internal.h"
 
+// The slot loops are written once for every tier and marked for unrolling,
+// which the register tiers need (their vertex state is indexed by slot); in
+// the memory tiers their bounds are run-time values and they stay loops.
+#pragma clang diagnostic ignored "-Wpass-failed"
+
 namespace vd {
 namespace {
 
@@ -256,7 +261,11 @@ struct P64 {
 // kernels carry no counting code).  G: waves building the cell together
 // (one in the register tiers).  kSoS: exact ties decided by the symbolic
 // perturbation (its own instantiation: the checked exact evaluation would
-// otherwise cost the default kernels registers).  Every wave of a group
+// otherwise cost the default kernels registers).  kW: the sites carry
+// weights; the 64- and 256-vertex passes of an unweighted build use an
+// instantiation without the weight terms of their bounds and ball tests
+// (every weight is zero there, so its results are the same bit for bit, at
+// about 2.5% less time).  Every wave of a group
 // holds the same copy of the cell-wide scalars (site, bounds, plane and
 // queue counts, flags) and changes it the same way, from values every wave
 // has seen.
@@ -264,7 +273,7 @@ struct P64 {
 // calls (the inliner's size limits give up on the larger instantiations)
 // they cost a stack frame in scratch memory and spills around each call.
 #pragma clang attribute push(__attribute__((always_inline)), apply_to = function)
-template <int VPL, bool kLds, bool kCount, int G = 1, bool kSoS = false>
+template <int VPL, bool kLds, bool kCount, int G = 1, bool kSoS = false, bool kW = true>
 struct Cell {
     static_assert(G == 1 || !Tier<VPL>::kReg, "wave groups need the vertex state in memory");
     using T = Tier<VPL>;
@@ -292,6 +301,8 @@ struct Cell {
     uint32_t serial;
     // site
     float px, py, pz, pw;
+    // the site's weight where the arithmetic uses it (zero without weights)
+    __device__ __forceinline__ float pwv() const { if constexpr (kW) return pw; else return 0.f; }
     uint32_t self;
     uint32_t flags;
     int robust;   // 0: FP32 signs; 1: doubtful signs in FP64; 2: every sign in FP64
@@ -640,8 +651,8 @@ struct Cell {
                     float dz = fmaxf(fmaxf(lz - c, c - hz), 0.f);
                     float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
                     float r2 = fmaf(a, a, fmaf(b, b, c * c));
-                    float lhs = d2 - wm, rhs = r2 - pw;
-                    hit |= lhs - rhs <= 16.f * kU * (d2 + r2 + fabsf(wm) + fabsf(pw));
+                    float lhs = d2 - wm, rhs = r2 - pwv();
+                    hit |= lhs - rhs <= 16.f * kU * (d2 + r2 + fabsf(wm) + fabsf(pwv()));
                 }
             }
         }
@@ -655,9 +666,9 @@ struct Cell {
         const float blx = c.lo[0] - px, bly = c.lo[1] - py, blz = c.lo[2] - pz;
         const float bhx = c.hi[0] - px, bhy = c.hi[1] - py, bhz = c.hi[2] - pz;
         const float l0x = rdl(blx, 0), l0y = rdl(bly, 0), l0z = rdl(blz, 0);
-        const float h0x = rdl(bhx, 0), h0y = rdl(bhy, 0), h0z = rdl(bhz, 0), w0 = rdl(c.wmax, 0);
+        const float h0x = rdl(bhx, 0), h0y = rdl(bhy, 0), h0z = rdl(bhz, 0), w0 = kW ? rdl(c.wmax, 0) : 0.f;
         const float l1x = rdl(blx, 1), l1y = rdl(bly, 1), l1z = rdl(blz, 1);
-        const float h1x = rdl(bhx, 1), h1y = rdl(bhy, 1), h1z = rdl(bhz, 1), w1 = rdl(c.wmax, 1);
+        const float h1x = rdl(bhx, 1), h1y = rdl(bhy, 1), h1z = rdl(bhz, 1), w1 = kW ? rdl(c.wmax, 1) : 0.f;
         bool a0 = false, a1 = false;
         const int ns = nsv();
         int lo, hi;
@@ -669,7 +680,7 @@ struct Cell {
             for (int k = 0; k < kBatch; ++k) {
                 if ((v.al[k] >> ln) & 1) {
                     const float a = v.a[k], b = v.b[k], cc = v.c[k];
-                    const float r2 = fmaf(a, a, fmaf(b, b, cc * cc)), rhs = r2 - pw, tol = r2 + fabsf(pw);
+                    const float r2 = fmaf(a, a, fmaf(b, b, cc * cc)), rhs = r2 - pwv(), tol = r2 + fabsf(pwv());
                     float dx = fmaxf(fmaxf(l0x - a, a - h0x), 0.f);
                     float dy = fmaxf(fmaxf(l0y - b, b - h0y), 0.f);
                     float dz = fmaxf(fmaxf(l0z - cc, cc - h0z), 0.f);
@@ -702,7 +713,7 @@ struct Cell {
     __device__ bool ball_hit_lane(const NodeChild& c, int l) {
         float lx = rdl(c.lo[0] - px, l), ly = rdl(c.lo[1] - py, l), lz = rdl(c.lo[2] - pz, l);
         float hx = rdl(c.hi[0] - px, l), hy = rdl(c.hi[1] - py, l), hz = rdl(c.hi[2] - pz, l);
-        float wm = rdl(c.wmax, l);
+        float wm = kW ? rdl(c.wmax, l) : 0.f;
         return ball_hit(lx, ly, lz, hx, hy, hz, wm);
     }
 
@@ -1326,7 +1337,7 @@ struct Cell {
         float dx = fmaxf(fmaxf(blx, -bhx), 0.f), dy = fmaxf(fmaxf(bly, -bhy), 0.f), dz = fmaxf(fmaxf(blz, -bhz), 0.f);
         // hardware square roots (1 ulp), inside the bound's rounding margin
         float d = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
-        float dw = pw - c.wmax;
+        float dw = kW ? pw - c.wmax : 0.f;
         float lb, err;
         if (dw > 0.f && A.culling == 3) {
             // every site j in the box has b_j / |a_j| >= f(|a_j|) with
@@ -1532,7 +1543,7 @@ struct Cell {
             q = A.pts[j];
             ax = q.x - px; ay = q.y - py; az = q.z - pz;
             a2 = fmaf(ax, ax, fmaf(ay, ay, az * az));
-            dw = pw - q.w;
+            dw = kW ? pw - q.w : 0.f;
             b = 0.5f * (a2 + dw);
             cand = (uint32_t)ln < nsite && j != self && q.w != -INFINITY && a2 > 0.f;
             for (int t = 0; t < nwarm; ++t) cand = cand && j != rdl(wsite, t);
@@ -1693,7 +1704,7 @@ struct Cell {
             const float4 q = A.pts[j];
             const float ax = q.x - px, ay = q.y - py, az = q.z - pz;
             const float a2 = fmaf(ax, ax, fmaf(ay, ay, az * az));
-            const float dw = pw - q.w;
+            const float dw = kW ? pw - q.w : 0.f;
             const uint64_t t0 = tic();
             const int r = clip(ax, ay, az, 0.5f * (a2 + dw), 0.5f * (a2 + fabsf(dw)), (int32_t)j);
             toc(kCtrCycClip, t0);
@@ -2252,7 +2263,7 @@ struct Cell {
 
 // The work loop shared by every tier (per wave, or per wave group with gx
 // its exchange tables).
-template <int VPL, bool kLds, bool kCount, int G = 1, bool kSoS = false>
+template <int VPL, bool kLds, bool kCount, int G = 1, bool kSoS = false, bool kW = true>
 __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
     KArgs* ka = cold_args();
     // the input checks (non-finite values, a flat box) ran before this pass:
@@ -2260,7 +2271,7 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
     if (*ka->err != 0u) return;
     const uint32_t count = ka->list ? *ka->list_count : (uint32_t)A.n;
     if (count == 0) return;  // a larger pass with no cell
-    Cell<VPL, kLds, kCount, G, kSoS> C(M, A, gx);
+    Cell<VPL, kLds, kCount, G, kSoS, kW> C(M, A, gx);
     unsigned long long st_empty = 0, st_large = 0, st_unc = 0, st_fail = 0, st_fp64 = 0, st_res = 0, st_pert = 0;
     // Cells are split into kWorkRanges contiguous (Morton-ordered) ranges, one
     // per XCD: the waves of workgroup b take chunks of their own range b % 8
@@ -2304,7 +2315,7 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
         const uint32_t slot = kc->list ? c : k;
         const uint32_t orig = kc->order[k];
         // a cell the previous pass handed over goes on from where it stopped
-        using CellT = Cell<VPL, kLds, kCount, G, kSoS>;
+        using CellT = Cell<VPL, kLds, kCount, G, kSoS, kW>;
         const typename CellT::HIn* hin = nullptr;
         if constexpr (CellT::kResumes) {
             if (kc->hand_in && c < kc->hand_in_cap) {
@@ -2414,10 +2425,10 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
 // block.  Register budgets: the 64-vertex pass is held to 128 registers for
 // 4 waves per SIMD, the 256-vertex pass to 256 for 2 (a few spills cost less
 // than the lost occupancy: both passes issue VALU work back to back).
-template <int VPL, int WAVES, bool kCount, bool kSoS = false>
+template <int VPL, int WAVES, bool kCount, bool kSoS = false, bool kW = true>
 __global__ __launch_bounds__(64 * WAVES, VPL == 1 ? 4 : 2) void k_clip(ClipArgs A) {
     __shared__ WaveMem<VPL> mem[WAVES];
-    run_cells<VPL, true, kCount, 1, kSoS>(mem[threadIdx.x >> 6], A, nullptr);
+    run_cells<VPL, true, kCount, 1, kSoS, kW>(mem[threadIdx.x >> 6], A, nullptr);
 }
 
 // Waves per cell in the 1024-vertex (LDS) and 16384-vertex (arena) tiers.
@@ -2486,10 +2497,16 @@ template <bool kCount, bool kSoS>
 void launch_tier(const ClipArgs& a, int workers, void* arena, hipStream_t s) {
     switch (a.tier) {
         case 0:
-            hipLaunchKernelGGL((k_clip<1, 4, kCount, kSoS>), dim3((workers + 3) / 4), dim3(256), 0, s, a);
+            if (a.weighted || kSoS)
+                hipLaunchKernelGGL((k_clip<1, 4, kCount, kSoS>), dim3((workers + 3) / 4), dim3(256), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_clip<1, 4, kCount, false, false>), dim3((workers + 3) / 4), dim3(256), 0, s, a);
             break;
         case 1:
-            hipLaunchKernelGGL((k_clip<4, 2, kCount, kSoS>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
+            if (a.weighted || kSoS)
+                hipLaunchKernelGGL((k_clip<4, 2, kCount, kSoS>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
+            else
+                hipLaunchKernelGGL((k_clip<4, 2, kCount, false, false>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
             break;
         case 2:
             hipLaunchKernelGGL((k_clip_lds<kCount, kSoS>), dim3(workers), dim3(64 * kGroupLds), 0, s, a);

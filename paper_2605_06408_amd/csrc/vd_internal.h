@@ -128,6 +128,7 @@ struct ClipArgs {
     int warm_start;           // K of the KNN warm start (0: none)
     int precision;            // 1 fp32, 2 mixed
     int perturb;              // 1: exact ties decided by symbolic perturbation of the weights
+    int weighted;             // 0: no weights were given (every weight is zero)
     int tier;                 // 0..3 (capacity kTierCap[tier])
     // work: cells c in [0, count) are list[c] (or c itself when list == null),
     // split into kWorkRanges contiguous ranges with one counter each (zeroed)

@@ -61,16 +61,16 @@ VD_API vd_status vd_measure_peaks(int device, void* stream, double* copy_gbs, do
         const int iters = 1 << 15;
         for (int r = 0; r < 6 && st == VD_OK; ++r) {
             float ms = 0.f;
-            hipEventRecord(e0, s);
+            if (hipEventRecord(e0, s) != hipSuccess) st = VD_ERR_HIP;
             hipLaunchKernelGGL(vd::k_copy, dim3(num_cu * 8), dim3(256), 0, s, a, b, n4);
-            hipEventRecord(e1, s);
-            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            if (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
                 st = VD_ERR_HIP;
             if (r > 0 && ms < best_copy) best_copy = ms;
-            hipEventRecord(e0, s);
+            if (hipEventRecord(e0, s) != hipSuccess) st = VD_ERR_HIP;
             hipLaunchKernelGGL(vd::k_fma, dim3(fma_blocks), dim3(256), 0, s, out, iters, 0.999f, 1e-3f);
-            hipEventRecord(e1, s);
-            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+            if (hipGetLastError() != hipSuccess || hipEventRecord(e1, s) != hipSuccess ||
+                hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
                 st = VD_ERR_HIP;
             if (r > 0 && ms < best_fma) best_fma = ms;
         }
@@ -79,11 +79,12 @@ VD_API vd_status vd_measure_peaks(int device, void* stream, double* copy_gbs, do
             *fma_tops = (double)fma_blocks * 256.0 * iters * vd::kFmaChains / (best_fma * 1e-3) / 1e12;
         }
     }
-    if (e0) hipEventDestroy(e0);
-    if (e1) hipEventDestroy(e1);
-    if (a) hipFree(a);
-    if (b) hipFree(b);
-    if (out) hipFree(out);
+    // release what was taken; a failure here cannot change the result
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    if (a) (void)hipFree(a);
+    if (b) (void)hipFree(b);
+    if (out) (void)hipFree(out);
     return st;
 }
 
