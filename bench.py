@@ -54,9 +54,9 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 # workload, each scaled by what the same counter reads for a plain 256 MiB
 # device copy in the same run.  Valid only while the kernel source is unchanged.
 TRAFFIC_MEASURED = {
-    "sources_sha1": {"paper_2605_06408_amd/csrc/vd_clip.hip": "203c522249632552571ca8577977e4e425afc4f6",
-                     "paper_2605_06408_amd/csrc/vd_internal.h": "f0bbf7e0269414dad7b4d7d51d914898968ff007"},
-    "workload": "clustered_1m", "fetch_kib": 56305.6875, "write_kib": 1101938.8125, "fetch_scale": 2.0,
+    "sources_sha1": {"paper_2605_06408_amd/csrc/vd_clip.hip": "9585f1f23a89558b52f60448738d914370861bb5",
+                     "paper_2605_06408_amd/csrc/vd_internal.h": "a9ffe624c746c7bc6000a4df20db078373875eb2"},
+    "workload": "clustered_1m", "fetch_kib": 53725.625, "write_kib": 1084290.25, "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
 
@@ -183,7 +183,7 @@ def run_leg(name, xyz, w, box, kw, steps, warmup, label, verbose=False):
     # dominant kernel: the 64-vertex pass, priced with its own counters
     k_ms = float(np.mean(clip_ms))
     wk = w_alg(ctr["tier0"])
-    kernel = {"kernel": "k_clip<1,4,false> (64-vertex pass)", "kernel_ms": k_ms, "w_alg": wk,
+    kernel = {"kernel": "k_clip<1, 4, ...> (64-vertex pass)", "kernel_ms": k_ms, "w_alg": wk,
               "achieved_Tops": wk / (k_ms * 1e-3) / 1e12, "frac": wk / (k_ms * 1e-3) / 1e12 / P_VALU_TOPS}
     # whole step
     W = w_alg(ctr["total"])

@@ -97,3 +97,24 @@ def test_surface_twenty_million(oracle_mod, seed):
     print("surface_20m seed %d: %d cells compared (%d of the larger passes, of %d)"
           % (seed, len(ids), int(((g["flags"] & 4) != 0).sum()), n_large))
     _check(rep, ids, rand, o)
+
+
+@pytest.mark.parametrize("name", ["clustered_1m", "power_uniform_1m", "power_clustered_1m", "surface_20m"])
+def test_cells_of_the_fp64_path(oracle_mod, name):
+    """Every cell of the default FP32 build that went through the FP64 path
+    (an inconsistent FP32 clip made it start over with doubtful signs
+    re-evaluated in FP64) against the oracle, held to the gate of that path:
+    exact match wherever the oracle certifies the cell at 1e-10.  These cells
+    lie within rounding of a degeneracy, so the FP32 gate of 1e-5 that the
+    random samples use would pass almost all of them by."""
+    xyz, w, box = wl.make(name, 0)
+    d = gpu_build(xyz, w, box)
+    ids = np.nonzero(d.flags.cpu().numpy() & 2)[0][:2000].astype(np.int64)
+    print("%s: %d cells took the FP64 path" % (name, len(ids)))
+    assert len(ids) == min(d.sizes["n_fp64"], 2000)
+    if len(ids) == 0:
+        return
+    g = to_numpy(d, ids)
+    o = oracle_mod.cells(xyz, w, box, ids=ids)
+    rep = compare(g, o, tau=1e-10)
+    assert_parity(rep, 0.0)
