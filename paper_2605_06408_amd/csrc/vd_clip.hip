@@ -49,6 +49,13 @@
 namespace vd {
 namespace {
 
+// node queue of the 64-vertex pass: kQueue0 entries, the first 64 in
+// registers (one per lane), the rest in LDS and touched only when the queue
+// is that long.  With one entry per vertex slot (64), cells of far-reaching
+// power cells and of sparse regions next to dense ones filled the queue long
+// before their vertex slots and went to the slower 256-vertex pass.
+constexpr int kQueue0 = 256;
+
 constexpr float kU = 5.9604645e-08f;  // FP32 unit roundoff 2^-24
 constexpr double kU64 = 1.1102230246251565e-16;
 
@@ -231,8 +238,17 @@ struct ArenaState<VPL, true> {
     uint64_t alive[VPL], R[VPL], fr[VPL];  // per-slot masks
 };
 
+// queue entries of the 64-vertex pass beyond the first 64
 template <int VPL>
-struct WaveMem : ArenaState<VPL> {
+struct QueueExt {};
+template <>
+struct QueueExt<1> {
+    uint32_t qxe[kQueue0 - 64];
+    float qxk[kQueue0 - 64];
+};
+
+template <int VPL>
+struct WaveMem : ArenaState<VPL>, QueueExt<VPL> {
     using W = typename Tier<VPL>::W;
     static constexpr int CAP = Tier<VPL>::CAP;
     float4 pl[CAP];        // planes: a.xyz, b (frame of the site)
@@ -287,7 +303,11 @@ struct Cell {
     static constexpr int kPrevCap = CAP == kTierCap[1] ? kTierCap[0]
                                     : (CAP == kTierCap[2] ? kTierCap[1] : (CAP == kTierCap[3] ? kTierCap[2] : 0));
     static constexpr bool kResumes = kPrevCap > 0;
-    using HIn = HandoffT<(kPrevCap > 0 ? kPrevCap : 64)>;
+    // queue capacity: one entry per vertex, but kQueue0 in the 64-vertex pass
+    static constexpr int QCAP = VPL == 1 ? kQueue0 : CAP;
+    static constexpr int kPrevQ = kPrevCap == 64 ? kQueue0 : kPrevCap;
+    using HIn = HandoffT<(kPrevCap > 0 ? kPrevCap : 64), (kPrevCap > 0 ? kPrevQ : 64)>;
+    using HOut = HandoffT<(kSaves ? CAP : 64), (kSaves ? QCAP : 64)>;
     template <typename X>
     using Lane = Col<X, VPL, kReg, 64>;  // one value per slot of this lane
     template <typename X>
@@ -322,7 +342,8 @@ struct Cell {
     // edges of the old cell)
     uint32_t ext[6];
     uint64_t cut_mask;
-    // queue (entry q in lane q % 64, slot q / 64)
+    // queue (entry q in lane q % 64, slot q / 64; in the 64-vertex pass entries
+    // from 64 on are in LDS, M.qxe / M.qxk)
     Lane<uint32_t> qe;
     Lane<float> qk;
     int qn;
@@ -1386,6 +1407,17 @@ struct Cell {
 
     __device__ void push(uint32_t e, float k) {
         const int slot = qn >> 6, l = qn & 63;
+        if constexpr (VPL == 1) {
+            if (slot > 0) {
+                if (ln == 0) {
+                    M.qxe[(slot - 1) * 64 + l] = e;
+                    M.qxk[(slot - 1) * 64 + l] = k;
+                }
+                wsync();  // read back by every lane
+                ++qn;
+                return;
+            }
+        }
         if constexpr (kReg) {
 #pragma unroll
             for (int s = 0; s < VPL; ++s)
@@ -1439,6 +1471,18 @@ struct Cell {
                     }
                 }
             }
+            if constexpr (VPL == 1) {
+                for (int s = 1; s < (qn + 63) >> 6; ++s) {
+                    const int idx = s * 64 + (int)ln;
+                    if (idx < qn) {
+                        const float kk = M.qxk[idx - 64];
+                        if (kk < bk) {
+                            bk = kk;
+                            bs = s;
+                        }
+                    }
+                }
+            }
             float m = wmin(bk);
             uint64_t msk = ballot(bk == m && (int)ln < qn);
             L = msk ? lowest(msk) : 0;
@@ -1447,6 +1491,34 @@ struct Cell {
         uint32_t ee = 0, le = 0;
         float kk = 0.f, lk = 0.f;
         const int last = qn - 1, ls = last >> 6, ll = last & 63;
+        if constexpr (VPL == 1) {
+            if (ls > 0) {  // entries beyond the first 64 (LDS)
+                if (S == 0) {
+                    ee = rdl(qe[0], L);
+                    kk = rdl(qk[0], L);
+                } else {
+                    ee = uni(M.qxe[(S - 1) * 64 + L]);
+                    kk = uni(M.qxk[(S - 1) * 64 + L]);
+                }
+                le = uni(M.qxe[last - 64]);
+                lk = uni(M.qxk[last - 64]);
+                if (S == 0) {
+                    if ((int)ln == L) {
+                        qe[0] = le;
+                        qk[0] = lk;
+                    }
+                } else {
+                    if (ln == 0) {
+                        M.qxe[(S - 1) * 64 + L] = le;
+                        M.qxk[(S - 1) * 64 + L] = lk;
+                    }
+                    wsync();
+                }
+                *e = ee;
+                *k = kk;
+                return;
+            }
+        }
         if constexpr (kReg) {
 #pragma unroll
             for (int s = 0; s < VPL; ++s)
@@ -1683,7 +1755,7 @@ struct Cell {
             for (int sd = 0; sd < 2; ++sd) {
                 const float dd = rdl(d, sd);
                 if (!(dd < worst)) continue;
-                if (qn >= CAP) {
+                if (qn >= QCAP) {
                     ok = false;  // queue full: go on with the nearest found so far
                     break;
                 }
@@ -1764,7 +1836,7 @@ struct Cell {
             const int L = 63 - __builtin_clzll(live);
             live &= ~(1ull << L);
             if (A.culling == 3 && !ball_hit_lane(c, L)) continue;
-            if (qn >= CAP) return kOverflow;
+            if (qn >= QCAP) return kOverflow;
             push(rdl(me, L), rdl(key, L));
         }
         return kNone;
@@ -1854,7 +1926,7 @@ struct Cell {
                 const int near = c1 ? 0 : (c0 ? 1 : (d0 <= d1 ? 0 : 1));
                 const int far = 1 - near;
                 if (!(far ? c1 : c0)) {
-                    if (qn >= CAP) return kOverflow;
+                    if (qn >= QCAP) return kOverflow;
                     push((node << 1) | (uint32_t)far, rdl(key, far));
                 }
                 cur = rdl(ref, near);
@@ -1911,7 +1983,7 @@ struct Cell {
     // ------------------------------------------------------------ hand-over
     // Writes the state of a cell that overflowed for the next pass; only the
     // header when the overflow is not resumable.
-    __device__ void save(HandoffT<(kSaves ? CAP : 64)>& H) {
+    __device__ void save(HOut& H) {
         if constexpr (kSaves) {
             sync();
             const int tid = (int)(wid * 64 + ln), step = 64 * G;
@@ -1935,6 +2007,12 @@ struct Cell {
                         H.qe[q] = qe[s];
                         H.qk[q] = qk[s];
                         if (ln == 0) H.alive[s] = alive[s];
+                    }
+                    if constexpr (VPL == 1) {
+                        for (int q = 64 + (int)ln; q < qn; q += 64) {
+                            H.qe[q] = M.qxe[q - 64];
+                            H.qk[q] = M.qxk[q - 64];
+                        }
                     }
                 } else {
                     for (int q = tid; q < vhi; q += step) {
@@ -2003,11 +2081,13 @@ struct Cell {
                         ev[s2] = H.ev[q];
                         vt[s2] = H.vt[q];
                         va[s2] = H.va[q];
-                        qe[s2] = H.qe[q];
-                        qk[s2] = H.qk[q];
                         alive[s2] = H.alive[s2];
                     } else {
                         alive[s2] = 0ull;
+                    }
+                    if (s2 < kPrevQ / 64) {
+                        qe[s2] = H.qe[q];
+                        qk[s2] = H.qk[q];
                     }
                 }
                 vhi = CAP;
@@ -2359,7 +2439,7 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
                     if constexpr (CellT::kSaves) {
                         pos = C.bcast(pos);
                         if (kn->hand_out && pos < kn->hand_out_cap)
-                            C.save(static_cast<HandoffT<CellT::CAP>*>(kn->hand_out)[pos]);
+                            C.save(static_cast<typename CellT::HOut*>(kn->hand_out)[pos]);
                     }
                     escalated = true;
                 } else {
@@ -2466,7 +2546,7 @@ size_t arena_bytes_per_worker() { return sizeof(WaveMem<kArenaVPL>); }
 
 size_t handoff_bytes(int tier) {
     switch (tier) {
-        case 0: return sizeof(HandoffT<kTierCap[0]>);
+        case 0: return sizeof(HandoffT<kTierCap[0], kQueue0>);
         case 1: return sizeof(HandoffT<kTierCap[1]>);
         case 2: return sizeof(HandoffT<kTierCap[2]>);
         default: return 0;

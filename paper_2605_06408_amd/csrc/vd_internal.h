@@ -88,10 +88,11 @@ enum CtrIndex { kCtrClassify = 0, kCtrNewVertex, kCtrNode, kCtrSite, kCtrFinal, 
 // leaf with its candidates not yet tried.  phase 0: the leaf was the site's
 // own leaf, clipped before any walk (the next pass finishes it, then walks
 // from the root passing over it); 1: a leaf of the walk (the next pass
-// finishes it, then goes on with the queue).  HC: capacity of the pass that
-// writes the record.
+// finishes it, then goes on with the queue).  HC: vertex capacity of the
+// pass that writes the record, QC: its queue capacity (larger than HC in the
+// 64-vertex pass).
 constexpr int kMaxWarm = 16;       // largest K of the KNN warm start
-template <int HC>
+template <int HC, int QC = HC>
 struct HandoffT {
     float4 pl[HC];            // planes: a.xyz, b
     float4 psite[HC];         // the plane's site
@@ -101,8 +102,8 @@ struct HandoffT {
     uint32_t vt[HC], va[HC];
     float psb[HC];
     int32_t pcode[HC];
-    uint32_t qe[HC];
-    float qk[HC];
+    uint32_t qe[QC];          // node queue (QC: the writer's queue capacity)
+    float qk[QC];
     uint32_t valid;           // 1: the state above can be resumed
     uint32_t np, vhi, qn, flags, robust, leaf, phase;
     uint32_t skip;            // a leaf the walk must pass over (already clipped), or kNoParent
