@@ -54,9 +54,9 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 # workload, each scaled by what the same counter reads for a plain 256 MiB
 # device copy in the same run.  Valid only while the kernel source is unchanged.
 TRAFFIC_MEASURED = {
-    "sources_sha1": {"paper_2605_06408_amd/csrc/vd_clip.hip": "9585f1f23a89558b52f60448738d914370861bb5",
-                     "paper_2605_06408_amd/csrc/vd_internal.h": "a9ffe624c746c7bc6000a4df20db078373875eb2"},
-    "workload": "clustered_1m", "fetch_kib": 53725.625, "write_kib": 1084290.25, "fetch_scale": 2.0,
+    "sources_sha1": {"paper_2605_06408_amd/csrc/vd_clip.hip": "99024e62358ed42d46e4016de6d961eb7dd7a7fb",
+                     "paper_2605_06408_amd/csrc/vd_internal.h": "efcfb4c0d3c5e26f32066e63a5bfd40a1859869f"},
+    "workload": "clustered_1m", "fetch_kib": 59303.625, "write_kib": 1100907.1875, "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
 
