@@ -120,11 +120,18 @@ hipError_t scan_u32(const uint32_t* in, int64_t n, uint32_t* out, uint32_t* tmp,
 
 // ------------------------------------------------------------------ writer
 
+// One group of kWriteLanes lanes per cell, several cells per wave: a cell has
+// a few dozen vertices and facets, and each one waits on a short chain of
+// dependent loads (its location, then its staged record), so more cells in
+// flight per wave is what fills the memory system.
+constexpr int kWriteLanes = 16;
+
 __global__ __launch_bounds__(256) void k_write(WriteArgs a) {
-    const int ln = threadIdx.x & 63;
-    const int64_t wave = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int64_t nwaves = ((int64_t)gridDim.x * blockDim.x) >> 6;
-    for (int64_t i = wave; i < a.n; i += nwaves) {
+    constexpr int LP = kWriteLanes;
+    const int ln = threadIdx.x & (LP - 1);
+    const int64_t grp = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / LP;
+    const int64_t ngrp = ((int64_t)gridDim.x * blockDim.x) / LP;
+    for (int64_t i = grp; i < a.n; i += ngrp) {
         const uint32_t k = a.inv[i];
         const uint32_t loc = a.loc[k];
         const uint32_t tier = loc >> 30;
@@ -137,7 +144,7 @@ __global__ __launch_bounds__(256) void k_write(WriteArgs a) {
         const uint16_t* FV = st.fv + slot * 3 * cap;
         const int nv = (int)a.cnt_v[i], nf = (int)a.cnt_f[i], nn = (int)a.cnt_n[i];
         const int64_t vo = a.off_v[i], fo = a.off_f[i], no = a.off_n[i];
-        for (int v = ln; v < nv; v += 64) {
+        for (int v = ln; v < nv; v += LP) {
             float4 q = V[v];
             uint32_t tri = __float_as_uint(q.w);
             if (a.vert) {
@@ -160,13 +167,13 @@ __global__ __launch_bounds__(256) void k_write(WriteArgs a) {
         }
         const int nbox = nf - nn;
         int64_t carry = 3 * vo;
-        for (int f0 = 0; f0 < nf; f0 += 64) {
+        for (int f0 = 0; f0 < nf; f0 += LP) {
             int f = f0 + ln;
             int32_t code = f < nf ? C[f] : 0;
             int64_t sz = f < nf ? (int64_t)FS[f] : 0;
             int64_t x = sz;
-            for (int o = 1; o < 64; o <<= 1) {
-                int64_t y = __shfl_up(x, o);
+            for (int o = 1; o < LP; o <<= 1) {
+                int64_t y = __shfl_up(x, o, LP);
                 if (ln >= o) x += y;
             }
             if (f < nf) {
@@ -174,16 +181,16 @@ __global__ __launch_bounds__(256) void k_write(WriteArgs a) {
                 if (a.fv_off) a.fv_off[fo + f] = carry + x - sz;
                 if (a.nbr && f >= nbox) a.nbr[no + (f - nbox)] = code;
             }
-            carry += __shfl(x, 63);
+            carry += __shfl(x, LP - 1, LP);
         }
         if (a.fv)
-            for (int t = ln; t < 3 * nv; t += 64) a.fv[3 * vo + t] = (int32_t)(vo + FV[t]);
+            for (int t = ln; t < 3 * nv; t += LP) a.fv[3 * vo + t] = (int32_t)(vo + FV[t]);
     }
 }
 
 hipError_t launch_write(const WriteArgs& a, hipStream_t s) {
-    int64_t waves = a.n < 65536 ? a.n : 65536;
-    int64_t blocks = (waves * 64 + 255) / 256;
+    const int64_t groups = a.n < 4 * 65536 ? a.n : 4 * 65536;
+    int64_t blocks = (groups * kWriteLanes + 255) / 256;
     if (blocks < 1) blocks = 1;
     hipLaunchKernelGGL(k_write, dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
