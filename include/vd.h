@@ -90,17 +90,17 @@ typedef struct vd_options {
 /* Phases reported by vd_get_timings (milliseconds, HIP events on `stream`). */
 #define VD_PHASE_LBVH 0       /* packing, Morton codes, radix sort, tree, bounds */
 #define VD_PHASE_CLIP 1       /* traversal + clipping, 64-vertex tier (one kernel) */
-#define VD_PHASE_CLIP_LARGE 2 /* traversal + clipping, 256-, 1024- and 16384-vertex tiers */
+#define VD_PHASE_CLIP_LARGE 2 /* traversal + clipping, 128-, 1024- and 16384-vertex tiers */
 #define VD_PHASE_SCAN 3       /* prefix sums of the per-cell counts */
 #define VD_PHASE_BUILD 4      /* the whole vd_build, first to last device operation */
 #define VD_PHASE_WRITE 5      /* vd_write (CSR write-out and copies) */
-#define VD_PHASE_CLIP_TIER1 6 /* the 256-vertex tier alone (part of VD_PHASE_CLIP_LARGE) */
+#define VD_PHASE_CLIP_TIER1 6 /* the 128-vertex tier alone (part of VD_PHASE_CLIP_LARGE) */
 #define VD_PHASE_BACKWARD 7   /* vd_backward */
 #define VD_PHASE_COUNT 8
 
 /* Work units counted when vd_options.counters = 1.  vd_get_counters returns
  * them per capacity tier: entry k + VD_CTR_COUNT * t is unit k of tier t
- * (t = 0: 64 vertices, 1: 256, 2: 1024, 3: 16384; VD_TIERS tiers). */
+ * (t = 0: 64 vertices, 1: 128, 2: 1024, 3: 16384; VD_TIERS tiers). */
 #define VD_TIERS 4
 #define VD_CTR_CLASSIFY 0     /* vertex-versus-plane side tests */
 #define VD_CTR_NEW_VERTEX 1   /* vertices created by clipping */

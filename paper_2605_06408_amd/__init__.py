@@ -35,7 +35,7 @@ TRAVERSAL_BEST_FIRST = 1
 TRAVERSAL_DEPTH_FIRST = 2
 
 MAX_SITES = 1 << 25
-TIERS = 4  # capacity tiers: 64, 256, 1024, 16384 vertices per cell
+TIERS = 4  # capacity tiers: 64, 128, 1024, 16384 vertices per cell
 
 PHASES = ("lbvh", "clip", "clip_large", "scan", "build", "write", "clip_tier1", "backward")
 COUNTERS = ("classify", "new_vertex", "node_test", "site_test", "final_vertex", "clip", "clip_effective", "leaf",
@@ -228,7 +228,7 @@ class Context:
 
     def counters(self) -> dict:
         """Work counters of the last build made with counters=True: a dict per
-        capacity tier ("tier0" .. "tier3": 64, 256, 1024, 16384 vertices) and
+        capacity tier ("tier0" .. "tier3": 64, 128, 1024, 16384 vertices) and
         their sum ("total")."""
         k = len(COUNTERS)
         v = (ctypes.c_uint64 * (TIERS * k))()

@@ -366,7 +366,7 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
             VD_TRY(ensure_stage(c, t, cap));
         }
         // hand-over records: every cell the 64-vertex pass may escalate, at
-        // most 8192 from the 256-vertex pass and 256 from the 1024-vertex pass
+        // most 8192 from the 128-vertex pass and 256 from the 1024-vertex pass
         static constexpr uint32_t kHandMax[vd::kTiers - 1] = {0xFFFFFFFFu, 8192u, 256u};
         uint32_t hand_cap[vd::kTiers - 1];
         for (int t = 0; t + 1 < vd::kTiers; ++t) {

@@ -27,7 +27,7 @@
 // each.
 //
 // Capacity tiers: 64 vertices (one slot; vertex state in registers, planes
-// and tables in LDS), 256 (four slots, same layout), 1024 (16 slots; every
+// and tables in LDS), 128 (two slots, same layout), 1024 (16 slots; every
 // per-cell array in LDS) and 16384 (256 slots; every per-cell array in an
 // arena in global memory).  In the last two a workgroup of several waves
 // builds one cell: the waves split every loop over vertex slots, combine
@@ -53,7 +53,7 @@ namespace {
 // registers (one per lane), the rest in LDS and touched only when the queue
 // is that long.  With one entry per vertex slot (64), cells of far-reaching
 // power cells and of sparse regions next to dense ones filled the queue long
-// before their vertex slots and went to the slower 256-vertex pass.
+// before their vertex slots and went to the slower second pass.
 constexpr int kQueue0 = 256;
 
 constexpr float kU = 5.9604645e-08f;  // FP32 unit roundoff 2^-24
@@ -246,6 +246,13 @@ struct QueueExt<1> {
     uint32_t qxe[kQueue0 - 64];
     float qxk[kQueue0 - 64];
 };
+template <>
+struct QueueExt<2> {
+    uint32_t qxe[kQueue0 - 128];
+    float qxk[kQueue0 - 128];
+};
+// queue capacity of the pass of vertex capacity cap
+constexpr int queue_cap(int cap) { return cap < kQueue0 ? kQueue0 : cap; }
 
 template <int VPL>
 struct WaveMem : ArenaState<VPL>, QueueExt<VPL> {
@@ -278,7 +285,7 @@ struct P64 {
 // (one in the register tiers).  kSoS: exact ties decided by the symbolic
 // perturbation (its own instantiation: the checked exact evaluation would
 // otherwise cost the default kernels registers).  kW: the sites carry
-// weights; the 64- and 256-vertex passes of an unweighted build use an
+// weights; the 64- and 128-vertex passes of an unweighted build use an
 // instantiation without the weight terms of their bounds and ball tests
 // (every weight is zero there, so its results are the same bit for bit, at
 // about 2.5% less time).  Every wave of a group
@@ -304,8 +311,9 @@ struct Cell {
                                     : (CAP == kTierCap[2] ? kTierCap[1] : (CAP == kTierCap[3] ? kTierCap[2] : 0));
     static constexpr bool kResumes = kPrevCap > 0;
     // queue capacity: one entry per vertex, but kQueue0 in the 64-vertex pass
-    static constexpr int QCAP = VPL == 1 ? kQueue0 : CAP;
-    static constexpr int kPrevQ = kPrevCap == 64 ? kQueue0 : kPrevCap;
+    static constexpr bool kQExt = kReg && 64 * VPL < kQueue0;  // queue entries beyond the slots in LDS
+    static constexpr int QCAP = queue_cap(CAP);
+    static constexpr int kPrevQ = kPrevCap > 0 ? queue_cap(kPrevCap) : 64;
     using HIn = HandoffT<(kPrevCap > 0 ? kPrevCap : 64), (kPrevCap > 0 ? kPrevQ : 64)>;
     using HOut = HandoffT<(kSaves ? CAP : 64), (kSaves ? QCAP : 64)>;
     template <typename X>
@@ -1407,11 +1415,11 @@ struct Cell {
 
     __device__ void push(uint32_t e, float k) {
         const int slot = qn >> 6, l = qn & 63;
-        if constexpr (VPL == 1) {
-            if (slot > 0) {
+        if constexpr (kQExt) {
+            if (slot >= VPL) {
                 if (ln == 0) {
-                    M.qxe[(slot - 1) * 64 + l] = e;
-                    M.qxk[(slot - 1) * 64 + l] = k;
+                    M.qxe[(slot - VPL) * 64 + l] = e;
+                    M.qxk[(slot - VPL) * 64 + l] = k;
                 }
                 wsync();  // read back by every lane
                 ++qn;
@@ -1471,11 +1479,11 @@ struct Cell {
                     }
                 }
             }
-            if constexpr (VPL == 1) {
-                for (int s = 1; s < (qn + 63) >> 6; ++s) {
+            if constexpr (kQExt) {
+                for (int s = VPL; s < (qn + 63) >> 6; ++s) {
                     const int idx = s * 64 + (int)ln;
                     if (idx < qn) {
-                        const float kk = M.qxk[idx - 64];
+                        const float kk = M.qxk[idx - 64 * VPL];
                         if (kk < bk) {
                             bk = kk;
                             bs = s;
@@ -1491,26 +1499,32 @@ struct Cell {
         uint32_t ee = 0, le = 0;
         float kk = 0.f, lk = 0.f;
         const int last = qn - 1, ls = last >> 6, ll = last & 63;
-        if constexpr (VPL == 1) {
-            if (ls > 0) {  // entries beyond the first 64 (LDS)
-                if (S == 0) {
-                    ee = rdl(qe[0], L);
-                    kk = rdl(qk[0], L);
+        if constexpr (kQExt) {
+            if (ls >= VPL) {  // the last entry is beyond the register slots (LDS)
+                if (S < VPL) {
+#pragma unroll
+                    for (int s = 0; s < VPL; ++s)
+                        if (s == S) {
+                            ee = rdl(qe[s], L);
+                            kk = rdl(qk[s], L);
+                        }
                 } else {
-                    ee = uni(M.qxe[(S - 1) * 64 + L]);
-                    kk = uni(M.qxk[(S - 1) * 64 + L]);
+                    ee = uni(M.qxe[(S - VPL) * 64 + L]);
+                    kk = uni(M.qxk[(S - VPL) * 64 + L]);
                 }
-                le = uni(M.qxe[last - 64]);
-                lk = uni(M.qxk[last - 64]);
-                if (S == 0) {
-                    if ((int)ln == L) {
-                        qe[0] = le;
-                        qk[0] = lk;
-                    }
+                le = uni(M.qxe[last - 64 * VPL]);
+                lk = uni(M.qxk[last - 64 * VPL]);
+                if (S < VPL) {
+#pragma unroll
+                    for (int s = 0; s < VPL; ++s)
+                        if (s == S && (int)ln == L) {
+                            qe[s] = le;
+                            qk[s] = lk;
+                        }
                 } else {
                     if (ln == 0) {
-                        M.qxe[(S - 1) * 64 + L] = le;
-                        M.qxk[(S - 1) * 64 + L] = lk;
+                        M.qxe[(S - VPL) * 64 + L] = le;
+                        M.qxk[(S - VPL) * 64 + L] = lk;
                     }
                     wsync();
                 }
@@ -1637,9 +1651,9 @@ struct Cell {
         };
         uint64_t mask = ballot(keep(cand));
         if constexpr (kResumes) mask &= allow;
-        // from 256 vertices up, the candidates that miss the cell are dropped
+        // from 128 vertices up, the candidates that miss the cell are dropped
         // all at once (not when every sign is taken in FP64)
-        if constexpr (G > 1 || VPL == 4) {
+        if constexpr (G > 1 || VPL >= 2) {
             if (mask && robust < 2) mask = cutting(mask, ax, ay, az, b, 0.5f * (a2 + fabsf(dw)));
         }
         while (mask) {
@@ -2008,10 +2022,10 @@ struct Cell {
                         H.qk[q] = qk[s];
                         if (ln == 0) H.alive[s] = alive[s];
                     }
-                    if constexpr (VPL == 1) {
-                        for (int q = 64 + (int)ln; q < qn; q += 64) {
-                            H.qe[q] = M.qxe[q - 64];
-                            H.qk[q] = M.qxk[q - 64];
+                    if constexpr (kQExt) {
+                        for (int q = 64 * VPL + (int)ln; q < qn; q += 64) {
+                            H.qe[q] = M.qxe[q - 64 * VPL];
+                            H.qk[q] = M.qxk[q - 64 * VPL];
                         }
                     }
                 } else {
@@ -2088,6 +2102,12 @@ struct Cell {
                     if (s2 < kPrevQ / 64) {
                         qe[s2] = H.qe[q];
                         qk[s2] = H.qk[q];
+                    }
+                }
+                if constexpr (kQExt) {
+                    for (int q = 64 * VPL + (int)ln; q < qn; q += 64) {
+                        M.qxe[q - 64 * VPL] = H.qe[q];
+                        M.qxk[q - 64 * VPL] = H.qk[q];
                     }
                 }
                 vhi = CAP;
@@ -2503,8 +2523,10 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
 
 // Register tiers: per-cell arrays in LDS, WAVES independent waves per
 // block.  Register budgets: the 64-vertex pass is held to 128 registers for
-// 4 waves per SIMD, the 256-vertex pass to 256 for 2 (a few spills cost less
-// than the lost occupancy: both passes issue VALU work back to back).
+// 4 waves per SIMD (a few spills cost less than the lost occupancy: the pass
+// issues VALU work back to back), the 128-vertex pass to 256 for 2 (its
+// cells are fewer and longer: at 3 waves per SIMD the spills of its two
+// slots made each cell slower than the occupancy gained).
 template <int VPL, int WAVES, bool kCount, bool kSoS = false, bool kW = true>
 __global__ __launch_bounds__(64 * WAVES, VPL == 1 ? 4 : 2) void k_clip(ClipArgs A) {
     __shared__ WaveMem<VPL> mem[WAVES];
@@ -2533,7 +2555,7 @@ __global__ __launch_bounds__(64 * kGroupArena) void k_clip_arena(ClipArgs A, Wav
     run_cells<kArenaVPL, false, kCount, kGroupArena, kSoS>(arena[blockIdx.x], A, gx);
 }
 
-static_assert(kTierCap[0] == 64 && kTierCap[1] == 256 && kTierCap[2] == 1024,
+static_assert(kTierCap[0] == 64 && kTierCap[1] == 128 && kTierCap[2] == 1024,
               "the LDS tiers are instantiated for 64, 256 and 1024 vertices");
 static_assert(sizeof(WaveMem<16>) + 2 * kGroupLds * 8 * sizeof(uint32_t) <= 160 * 1024,
               "the 1024-vertex tier must fit the LDS of one CU");
@@ -2547,7 +2569,7 @@ size_t arena_bytes_per_worker() { return sizeof(WaveMem<kArenaVPL>); }
 size_t handoff_bytes(int tier) {
     switch (tier) {
         case 0: return sizeof(HandoffT<kTierCap[0], kQueue0>);
-        case 1: return sizeof(HandoffT<kTierCap[1]>);
+        case 1: return sizeof(HandoffT<kTierCap[1], kQueue0>);
         case 2: return sizeof(HandoffT<kTierCap[2]>);
         default: return 0;
     }
@@ -2560,7 +2582,7 @@ int clip_grid_workers(int tier, int num_cu) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip<1, 4, false>, 256, 0);
         per_cu *= 4;
     } else if (tier == 1) {
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip<4, 2, false>, 128, 0);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip<2, 2, false>, 128, 0);
         per_cu *= 2;
     } else if (tier == 2) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_clip_lds<false>, 64 * kGroupLds, 0);
@@ -2584,9 +2606,9 @@ void launch_tier(const ClipArgs& a, int workers, void* arena, hipStream_t s) {
             break;
         case 1:
             if (a.weighted || kSoS)
-                hipLaunchKernelGGL((k_clip<4, 2, kCount, kSoS>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
+                hipLaunchKernelGGL((k_clip<2, 2, kCount, kSoS>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
             else
-                hipLaunchKernelGGL((k_clip<4, 2, kCount, false, false>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
+                hipLaunchKernelGGL((k_clip<2, 2, kCount, false, false>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
             break;
         case 2:
             hipLaunchKernelGGL((k_clip_lds<kCount, kSoS>), dim3(workers), dim3(64 * kGroupLds), 0, s, a);

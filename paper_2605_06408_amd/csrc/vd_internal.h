@@ -17,7 +17,7 @@ constexpr int kDefaultLeaf = 32;
 constexpr int kWorkRanges = 8;
 // Vertex (= plane) capacity of a cell in each clipping pass.
 constexpr int kTiers = 4;
-constexpr int kTierCap[kTiers] = {64, 256, 1024, 16384};
+constexpr int kTierCap[kTiers] = {64, 128, 1024, 16384};
 
 // ---------------------------------------------------------------- BVH
 

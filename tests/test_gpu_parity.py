@@ -225,7 +225,7 @@ def test_partition_invariants_on_gpu():
 def _heavy_sites(n, seed):
     """Uniform sites, the first four made heavy (w = r^2): their power cells
     have about 3700, 1000, 450 and 220 vertices, so they are built by the
-    16384-, 1024- and 256-vertex passes."""
+    16384-, 1024- and 128-vertex passes."""
     rng = np.random.default_rng(seed)
     xyz = rng.random((n, 3)).astype(np.float32)
     w = np.zeros(n, np.float32)
@@ -311,7 +311,7 @@ def _hedgehogs(m, per, seed):
 
 
 def test_more_large_cells_than_the_first_slots(oracle_mod):
-    """A fresh context stages at most max(1024, n/64) cells of the 256-vertex
+    """A fresh context stages at most max(1024, n/64) cells of the 128-vertex
     pass; 1100 centres each needing that pass exceed it, so the first build
     leaves cells undone, grows its buffers and runs the passes again.  The
     result must match the oracle and a second build (no retry) exactly."""
