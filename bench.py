@@ -54,9 +54,9 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 # workload, each scaled by what the same counter reads for a plain 256 MiB
 # device copy in the same run.  Valid only while the kernel source is unchanged.
 TRAFFIC_MEASURED = {
-    "sources_sha1": {"paper_2605_06408_amd/csrc/vd_clip.hip": "99024e62358ed42d46e4016de6d961eb7dd7a7fb",
-                     "paper_2605_06408_amd/csrc/vd_internal.h": "efcfb4c0d3c5e26f32066e63a5bfd40a1859869f"},
-    "workload": "clustered_1m", "fetch_kib": 59303.625, "write_kib": 1100907.1875, "fetch_scale": 2.0,
+    "sources_sha1": {"paper_2605_06408_amd/csrc/vd_clip.hip": "45c7ccd698f888b037a51e2cd8404de3dcab4423",
+                     "paper_2605_06408_amd/csrc/vd_internal.h": "77d985737103a5e17fcf0f4b9b37769ea8224b30"},
+    "workload": "clustered_1m", "fetch_kib": 55258.3125, "write_kib": 1100524.75, "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
 
