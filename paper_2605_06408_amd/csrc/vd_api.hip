@@ -337,9 +337,9 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
     // The clipping passes run back to back with no host synchronisation: the
     // larger passes are launched with persistent grids that read their cell
     // counts from device memory, on buffers sized beforehand for at least a
-    // floor of cells (n/64, n/4096 and 16 for the 256-, 1024- and
-    // 16384-vertex passes) and at least as many as earlier builds on this
-    // context needed.  A pass with more cells than slots leaves the extra ones
+    // floor of cells (n/64 and n/1024, at least 1024 each, and 16 for the
+    // 128-, 1024- and 16384-vertex passes) and at least as many as earlier
+    // builds on this context needed.  A pass with more cells than slots leaves the extra ones
     // undone and counts them; the one synchronisation at the end then sees the
     // counts, the buffers grow, and the passes run again (a first build of a
     // larger workload; the LBVH is kept).
@@ -356,8 +356,8 @@ VD_API vd_status vd_build(vd_context* c, const float* xyz, const float* w, int64
         uint32_t slots[vd::kTiers];
         slots[0] = (uint32_t)n;
         for (int t = 1; t < vd::kTiers; ++t) {
-            static constexpr uint32_t kDiv[vd::kTiers] = {1u, 64u, 4096u, 0u};
-            static constexpr uint32_t kFloor[vd::kTiers] = {0u, 1024u, 256u, 16u};
+            static constexpr uint32_t kDiv[vd::kTiers] = {1u, 64u, 1024u, 0u};
+            static constexpr uint32_t kFloor[vd::kTiers] = {0u, 1024u, 1024u, 16u};
             uint64_t cap = kDiv[t] ? (uint64_t)n / kDiv[t] : 0;
             if (cap < kFloor[t]) cap = kFloor[t];
             if (cap < c->seen[t]) cap = c->seen[t];
