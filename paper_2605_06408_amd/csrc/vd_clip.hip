@@ -285,10 +285,13 @@ struct P64 {
 // (one in the register tiers).  kSoS: exact ties decided by the symbolic
 // perturbation (its own instantiation: the checked exact evaluation would
 // otherwise cost the default kernels registers).  kW: the sites carry
-// weights; the 64- and 128-vertex passes of an unweighted build use an
-// instantiation without the weight terms of their bounds and ball tests
-// (every weight is zero there, so its results are the same bit for bit, at
-// about 2.5% less time).  Every wave of a group
+// weights; kOpt: the search options (culling, traversal order, warm start)
+// are read at run time.  The 64- and 128-vertex passes of a build with the
+// default options run instantiations with those options fixed, and for an
+// unweighted build without the weight terms of the bounds and ball tests
+// (every weight is zero there): the same results bit for bit, 4% less time
+// for the fixed options (their checks and the scalar registers they held)
+// and 2.5% for the weight terms.  Every wave of a group
 // holds the same copy of the cell-wide scalars (site, bounds, plane and
 // queue counts, flags) and changes it the same way, from values every wave
 // has seen.
@@ -296,7 +299,7 @@ struct P64 {
 // calls (the inliner's size limits give up on the larger instantiations)
 // they cost a stack frame in scratch memory and spills around each call.
 #pragma clang attribute push(__attribute__((always_inline)), apply_to = function)
-template <int VPL, bool kLds, bool kCount, int G = 1, bool kSoS = false, bool kW = true>
+template <int VPL, bool kLds, bool kCount, int G = 1, bool kSoS = false, bool kW = true, bool kOpt = true>
 struct Cell {
     static_assert(G == 1 || !Tier<VPL>::kReg, "wave groups need the vertex state in memory");
     using T = Tier<VPL>;
@@ -331,6 +334,11 @@ struct Cell {
     float px, py, pz, pw;
     // the site's weight where the arithmetic uses it (zero without weights)
     __device__ __forceinline__ float pwv() const { if constexpr (kW) return pw; else return 0.f; }
+    // search options: the default instantiations fix them (directional plus
+    // ball culling, best-first order, no warm start)
+    __device__ __forceinline__ int culling() const { if constexpr (kOpt) return A.culling; else return 3; }
+    __device__ __forceinline__ int traversal() const { if constexpr (kOpt) return A.traversal; else return 1; }
+    __device__ __forceinline__ int warm_start() const { if constexpr (kOpt) return A.warm_start; else return 0; }
     uint32_t self;
     uint32_t flags;
     int robust;   // 0: FP32 signs; 1: doubtful signs in FP64; 2: every sign in FP64
@@ -582,13 +590,13 @@ struct Cell {
                     const float a = v.a[k], b = v.b[k], c = v.c[k];
                     mn0 = fminf(mn0, a); mn1 = fminf(mn1, b); mn2 = fminf(mn2, c);
                     mx0 = fmaxf(mx0, a); mx1 = fmaxf(mx1, b); mx2 = fmaxf(mx2, c);
-                    if (A.culling == 2) r2 = fmaxf(r2, fmaf(a, a, fmaf(b, b, c * c)));
+                    if (culling() == 2) r2 = fmaxf(r2, fmaf(a, a, fmaf(b, b, c * c)));
                 }
             }
         }
         float l0 = wmin(mn0), l1 = wmin(mn1), l2 = wmin(mn2);
         float h0 = wmax(mx0), h1 = wmax(mx1), h2 = wmax(mx2);
-        riso2 = A.culling == 2 ? wmax(r2) : 0.f;  // the isotropic radius only serves culling mode 2
+        riso2 = culling() == 2 ? wmax(r2) : 0.f;  // the isotropic radius only serves culling mode 2
         if constexpr (G > 1) {
             const uint32_t v[7] = {__float_as_uint(l0), __float_as_uint(l1), __float_as_uint(l2), __float_as_uint(h0),
                                    __float_as_uint(h1), __float_as_uint(h2), __float_as_uint(riso2)};
@@ -628,7 +636,7 @@ struct Cell {
     // vertex the clip removed are reduced again.
     __device__ void bounds_after_clip() {
         if constexpr (VPL == 1 && G == 1) {
-            if (A.culling != 2) {
+            if (culling() != 2) {
                 uint32_t lost = 0;
 #pragma unroll
                 for (int k = 0; k < 6; ++k) lost |= (uint32_t)((cut_mask >> ext[k]) & 1ull) << k;
@@ -654,7 +662,7 @@ struct Cell {
     // Squared radius of the cell toward direction a (far AABB corner of the
     // octant of a; zero components count as positive).
     __device__ __forceinline__ float radius2_toward(float ax, float ay, float az) const {
-        if (A.culling == 2) return riso2;
+        if (culling() == 2) return riso2;
         return (ax >= 0.f ? hx2 : lx2) + (ay >= 0.f ? hy2 : ly2) + (az >= 0.f ? hz2 : lz2);
     }
 
@@ -1368,7 +1376,7 @@ struct Cell {
         float d = __builtin_amdgcn_sqrtf(fmaf(dx, dx, fmaf(dy, dy, dz * dz)));
         float dw = kW ? pw - c.wmax : 0.f;
         float lb, err;
-        if (dw > 0.f && A.culling == 3) {
+        if (dw > 0.f && culling() == 3) {
             // every site j in the box has b_j / |a_j| >= f(|a_j|) with
             // f(t) = t/2 + dw/(2t), and |a_j| lies between the box's nearest
             // and farthest distances: the bound is f at sqrt(dw) clamped to
@@ -1396,7 +1404,7 @@ struct Cell {
             err = 0.f;
         }
         float rb2;
-        if (A.culling == 2) {
+        if (culling() == 2) {
             rb2 = riso2;
         } else {
             // per axis: the far-corner square of each side the box reaches
@@ -1448,7 +1456,7 @@ struct Cell {
     __device__ void pop(uint32_t* e, float* k, bool least = false) {
         uint32_t ee = 0;
         float kk = 0.f;
-        if (lead()) pop_lead(&ee, &kk, least || A.traversal != 2);
+        if (lead()) pop_lead(&ee, &kk, least || traversal() != 2);
         if constexpr (G > 1) {
             const uint32_t v[2] = {ee, __float_as_uint(kk)};
             const uint32_t* t = exch(v);
@@ -1638,7 +1646,7 @@ struct Cell {
         const float sbl = 0.5f * (a2 + fabsf(dw));  // size of the terms of b (error scale)
         auto keep = [&](bool c) -> bool {
             if (!c) return false;
-            if (A.culling == 3) {
+            if (culling() == 3) {
                 // the plane misses the cell's AABB: max over the box of a.y <= b
                 float cx = ax >= 0.f ? bhi0 : blo0, cy = ay >= 0.f ? bhi1 : blo1, cz = az >= 0.f ? bhi2 : blo2;
                 float mm = fmaf(ax, cx, fmaf(ay, cy, az * cz));
@@ -1849,7 +1857,7 @@ struct Cell {
         while (live) {
             const int L = 63 - __builtin_clzll(live);
             live &= ~(1ull << L);
-            if (A.culling == 3 && !ball_hit_lane(c, L)) continue;
+            if (culling() == 3 && !ball_hit_lane(c, L)) continue;
             if (qn >= QCAP) return kOverflow;
             push(rdl(me, L), rdl(key, L));
         }
@@ -1887,8 +1895,8 @@ struct Cell {
         // made the larger passes 40-60% slower on the power and surface
         // workloads)
         if (!resume && A.leaf_of != nullptr) {
-            if (A.warm_start > 0) {
-                const int rw = knn_warm(A.warm_start);
+            if (warm_start() > 0) {
+                const int rw = knn_warm(warm_start());
                 if constexpr (kSaves) ov_ok = false;  // an overflow in the warm start starts over
                 if (rw != kNone) return rw;
             }
@@ -1917,7 +1925,7 @@ struct Cell {
                 ref = cc.ref;
                 const uint64_t cm = ballot(cull);
                 bool c0 = (cm & 1ull) != 0, c1 = (cm & 2ull) != 0;
-                if (A.culling == 3) {
+                if (culling() == 3) {
                     if (!c0 && !c1) {
                         bool h0, h1;
                         ball_hit_pair(cc, &h0, &h1);
@@ -1971,7 +1979,7 @@ struct Cell {
                 float k;
                 pop(&e, &k);
                 count(kCtrNode, 1);
-                if (A.traversal != 2 && k > __builtin_amdgcn_sqrtf(rmax2) * (1.f + 16.f * kU)) {
+                if (traversal() != 2 && k > __builtin_amdgcn_sqrtf(rmax2) * (1.f + 16.f * kU)) {
                     qn = 0;  // every key left is at least k: nothing can cut the cell
                     break;
                 }
@@ -1983,7 +1991,7 @@ struct Cell {
                 node_test(c, &key, &cull, &delta);
                 ref = c.ref;
                 bool culled = rdl((int)cull, 0) != 0;
-                if (!culled && A.culling == 3 && !ball_hit_lane(c, 0)) culled = true;
+                if (!culled && culling() == 3 && !ball_hit_lane(c, 0)) culled = true;
                 if (!culled) {
                     cur = rdl(ref, 0);
                     have = true;
@@ -2363,7 +2371,7 @@ struct Cell {
 
 // The work loop shared by every tier (per wave, or per wave group with gx
 // its exchange tables).
-template <int VPL, bool kLds, bool kCount, int G = 1, bool kSoS = false, bool kW = true>
+template <int VPL, bool kLds, bool kCount, int G = 1, bool kSoS = false, bool kW = true, bool kOpt = true>
 __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
     KArgs* ka = cold_args();
     // the input checks (non-finite values, a flat box) ran before this pass:
@@ -2371,7 +2379,7 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
     if (*ka->err != 0u) return;
     const uint32_t count = ka->list ? *ka->list_count : (uint32_t)A.n;
     if (count == 0) return;  // a larger pass with no cell
-    Cell<VPL, kLds, kCount, G, kSoS, kW> C(M, A, gx);
+    Cell<VPL, kLds, kCount, G, kSoS, kW, kOpt> C(M, A, gx);
     unsigned long long st_empty = 0, st_large = 0, st_unc = 0, st_fail = 0, st_fp64 = 0, st_res = 0, st_pert = 0;
     // Cells are split into kWorkRanges contiguous (Morton-ordered) ranges, one
     // per XCD: the waves of workgroup b take chunks of their own range b % 8
@@ -2415,7 +2423,7 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
         const uint32_t slot = kc->list ? c : k;
         const uint32_t orig = kc->order[k];
         // a cell the previous pass handed over goes on from where it stopped
-        using CellT = Cell<VPL, kLds, kCount, G, kSoS, kW>;
+        using CellT = Cell<VPL, kLds, kCount, G, kSoS, kW, kOpt>;
         const typename CellT::HIn* hin = nullptr;
         if constexpr (CellT::kResumes) {
             if (kc->hand_in && c < kc->hand_in_cap) {
@@ -2527,10 +2535,10 @@ __device__ void run_cells(WaveMem<VPL>& M, const ClipArgs& A, uint32_t* gx) {
 // issues VALU work back to back), the 128-vertex pass to 256 for 2 (its
 // cells are fewer and longer: at 3 waves per SIMD the spills of its two
 // slots made each cell slower than the occupancy gained).
-template <int VPL, int WAVES, bool kCount, bool kSoS = false, bool kW = true>
+template <int VPL, int WAVES, bool kCount, bool kSoS = false, bool kW = true, bool kOpt = true>
 __global__ __launch_bounds__(64 * WAVES, VPL == 1 ? 4 : 2) void k_clip(ClipArgs A) {
     __shared__ WaveMem<VPL> mem[WAVES];
-    run_cells<VPL, true, kCount, 1, kSoS, kW>(mem[threadIdx.x >> 6], A, nullptr);
+    run_cells<VPL, true, kCount, 1, kSoS, kW, kOpt>(mem[threadIdx.x >> 6], A, nullptr);
 }
 
 // Waves per cell in the 1024-vertex (LDS) and 16384-vertex (arena) tiers.
@@ -2597,18 +2605,24 @@ int clip_grid_workers(int tier, int num_cu) {
 
 template <bool kCount, bool kSoS>
 void launch_tier(const ClipArgs& a, int workers, void* arena, hipStream_t s) {
+    // the register passes have instantiations with the default search options fixed
+    const bool def = a.culling == 3 && a.traversal == 1 && a.warm_start == 0;
     switch (a.tier) {
         case 0:
-            if (a.weighted || kSoS)
+            if (kSoS || !def)
                 hipLaunchKernelGGL((k_clip<1, 4, kCount, kSoS>), dim3((workers + 3) / 4), dim3(256), 0, s, a);
+            else if (a.weighted)
+                hipLaunchKernelGGL((k_clip<1, 4, kCount, false, true, false>), dim3((workers + 3) / 4), dim3(256), 0, s, a);
             else
-                hipLaunchKernelGGL((k_clip<1, 4, kCount, false, false>), dim3((workers + 3) / 4), dim3(256), 0, s, a);
+                hipLaunchKernelGGL((k_clip<1, 4, kCount, false, false, false>), dim3((workers + 3) / 4), dim3(256), 0, s, a);
             break;
         case 1:
-            if (a.weighted || kSoS)
+            if (kSoS || !def)
                 hipLaunchKernelGGL((k_clip<2, 2, kCount, kSoS>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
+            else if (a.weighted)
+                hipLaunchKernelGGL((k_clip<2, 2, kCount, false, true, false>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
             else
-                hipLaunchKernelGGL((k_clip<2, 2, kCount, false, false>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
+                hipLaunchKernelGGL((k_clip<2, 2, kCount, false, false, false>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
             break;
         case 2:
             hipLaunchKernelGGL((k_clip_lds<kCount, kSoS>), dim3(workers), dim3(64 * kGroupLds), 0, s, a);
