@@ -54,9 +54,9 @@ PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 # workload, each scaled by what the same counter reads for a plain 256 MiB
 # device copy in the same run.  Valid only while the kernel source is unchanged.
 TRAFFIC_MEASURED = {
-    "sources_sha1": {"paper_2605_06408_amd/csrc/vd_clip.hip": "45c7ccd698f888b037a51e2cd8404de3dcab4423",
+    "sources_sha1": {"paper_2605_06408_amd/csrc/vd_clip.hip": "8b7a529a5af7ea0e90c41faeb3f8d35f56feccdd",
                      "paper_2605_06408_amd/csrc/vd_internal.h": "77d985737103a5e17fcf0f4b9b37769ea8224b30"},
-    "workload": "clustered_1m", "fetch_kib": 55258.3125, "write_kib": 1100524.75, "fetch_scale": 2.0,
+    "workload": "clustered_1m", "fetch_kib": 54281.5, "write_kib": 1088839.78125, "fetch_scale": 2.0,
     "write_scale": 1.0,
 }
 
