@@ -2609,20 +2609,20 @@ void launch_tier(const ClipArgs& a, int workers, void* arena, hipStream_t s) {
     const bool def = a.culling == 3 && a.traversal == 1 && a.warm_start == 0;
     switch (a.tier) {
         case 0:
-            if (!def)
+            if (kSoS || !def)
                 hipLaunchKernelGGL((k_clip<1, 4, kCount, kSoS>), dim3((workers + 3) / 4), dim3(256), 0, s, a);
             else if (a.weighted)
-                hipLaunchKernelGGL((k_clip<1, 4, kCount, kSoS, true, false>), dim3((workers + 3) / 4), dim3(256), 0, s, a);
+                hipLaunchKernelGGL((k_clip<1, 4, kCount, false, true, false>), dim3((workers + 3) / 4), dim3(256), 0, s, a);
             else
-                hipLaunchKernelGGL((k_clip<1, 4, kCount, kSoS, false, false>), dim3((workers + 3) / 4), dim3(256), 0, s, a);
+                hipLaunchKernelGGL((k_clip<1, 4, kCount, false, false, false>), dim3((workers + 3) / 4), dim3(256), 0, s, a);
             break;
         case 1:
-            if (!def)
+            if (kSoS || !def)
                 hipLaunchKernelGGL((k_clip<2, 2, kCount, kSoS>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
             else if (a.weighted)
-                hipLaunchKernelGGL((k_clip<2, 2, kCount, kSoS, true, false>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
+                hipLaunchKernelGGL((k_clip<2, 2, kCount, false, true, false>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
             else
-                hipLaunchKernelGGL((k_clip<2, 2, kCount, kSoS, false, false>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
+                hipLaunchKernelGGL((k_clip<2, 2, kCount, false, false, false>), dim3((workers + 1) / 2), dim3(128), 0, s, a);
             break;
         case 2:
             hipLaunchKernelGGL((k_clip_lds<kCount, kSoS>), dim3(workers), dim3(64 * kGroupLds), 0, s, a);
